@@ -1,0 +1,168 @@
+/*
+ * pdfs.h -- C ABI of the MI355X P-DFS / greedy weighted-set-cover library.
+ *
+ * The library finds h-hit gene combinations the way the paper's pruned
+ * depth-first search does (Sec. III-C, Alg. 2) inside the standard greedy
+ * weighted-set-cover loop (Sec. II-C, Alg. 1), on one AMD Instinct GPU.
+ *
+ * Problem (Sec. II-B, Eq. 1): tumour matrix T (G genes x N_t samples) and
+ * normal matrix N (G x N_n), both 0/1.  A combination gamma of h distinct
+ * genes covers a sample when every gene of gamma is mutated in it.  With the
+ * still-uncovered tumour samples U of the current round:
+ *     TP = |cover_T(gamma) & U|,  FP = |cover_N(gamma)|,  TN = N_n - FP,
+ *     S  = p*TP + q*TN            (integer numerator of the score)
+ * F(gamma) = (alpha*TP + TN) / (|U| + N_n) with alpha = p/q (Sec. II-C), so
+ * F = S / (q*(|U| + N_n)); the denominator is shared by all candidates of a
+ * round, so candidates are ranked by S, exactly, in integers.
+ * Each round picks, among the combinations with TP >= 1, the largest S; ties
+ * go to the lexicographically smallest tuple of sorted gene indices (the
+ * order a sequential depth-first maximum search with a strict ">" keeps).
+ * Genes are sorted once, sparsest first (Sec. III-B): ascending combined
+ * tumour+normal mutation count, ties by caller index.  The round's cover is
+ * then removed from U (DelCols of Alg. 1, tumour columns only) and the loop
+ * repeats until the covered count reaches the target, no combination has
+ * TP >= 1, or the round cap is hit.
+ *
+ * Bit layout: a matrix is row-major uint64 words, one row per gene; sample s
+ * of gene g is bit (s & 63) of word row[g*stride + (s >> 6)].  Bits past the
+ * sample count must be 0 (PDFS_ERR_INVALID_ARG otherwise).
+ *
+ * Errors: every call returns an int32 status; nothing is thrown across the
+ * ABI.  Negative values are errors, 0 is success, positive values are
+ * informational.  pdfs_strerror() names a status; pdfs_last_error() gives the
+ * detail of the last failing call on a context.
+ *
+ * Threading: a context may be used by one host thread at a time; distinct
+ * contexts are independent.  Work is issued on the stream given at creation
+ * (NULL = the device's null stream); calls return after their results are on
+ * the host.
+ */
+#ifndef PDFS_H
+#define PDFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define PDFS_OK 0
+#define PDFS_NO_COMBO 1            /* no h-subset covers an uncovered sample   */
+#define PDFS_PENDING 2             /* server: request not finished yet         */
+#define PDFS_ERR_INVALID_ARG (-1)  /* bad argument, layout or pad bits          */
+#define PDFS_ERR_UNSUPPORTED (-2)  /* valid but outside what the GPU path runs  */
+#define PDFS_ERR_OUT_OF_MEMORY (-3)/* device allocation or admission failure    */
+#define PDFS_ERR_DEVICE (-4)       /* HIP runtime / kernel error                */
+#define PDFS_ERR_TRUNCATED (-5)    /* output array too small; *n_out = needed   */
+
+/* ------------------------------------------------------------ pruning modes */
+/* PDFS_PRUNE_EMPTY: the paper's rule (Alg. 2) -- a prefix whose running tumour
+ *   intersection is empty is not extended.
+ * PDFS_PRUNE_BOUND: EMPTY plus the score bound of Sec. III-E -- a prefix
+ *   covering c uncovered tumour samples can reach at most p*c + q*N_n, so it
+ *   is not extended when that cannot beat the best combination found so far.
+ *   Exact: it returns the same combinations as EMPTY.  The default.
+ * PDFS_PRUNE_NONE: exhaustive enumeration; accepted by the interface but the
+ *   GPU path returns PDFS_ERR_UNSUPPORTED for it. */
+#define PDFS_PRUNE_NONE 0
+#define PDFS_PRUNE_EMPTY 1
+#define PDFS_PRUNE_BOUND 2
+
+#define PDFS_MAX_H 8
+
+typedef struct pdfs_ctx pdfs_ctx;
+
+/* Input cohort.  tumor: G rows x tumor_stride_words uint64 (stride >=
+ * ceil(n_tumor/64)); normal: G rows x normal_stride_words (stride >=
+ * ceil(n_normal/64); may be NULL when n_normal == 0).  on_device != 0 means
+ * both pointers are device pointers on the context's device.  The library
+ * copies the data; the caller keeps ownership and may free it on return. */
+typedef struct {
+    int32_t G;
+    int32_t n_tumor;   /* >= 1   */
+    int32_t n_normal;  /* >= 0   */
+    int32_t on_device;
+    const uint64_t *tumor;
+    const uint64_t *normal;
+    int64_t tumor_stride_words;
+    int64_t normal_stride_words;
+} pdfs_matrix;
+
+typedef struct {
+    int32_t prune_mode; /* PDFS_PRUNE_*                                  */
+    int32_t device;     /* HIP device ordinal                            */
+    void *stream;       /* hipStream_t on that device, or NULL           */
+} pdfs_options;
+
+/* One chosen combination (one greedy round). */
+typedef struct {
+    int32_t h;
+    int32_t genes[PDFS_MAX_H];      /* caller gene ids, in sorted order          */
+    int32_t sorted_idx[PDFS_MAX_H]; /* the same genes as sorted (sparsest-first) indices */
+    int32_t tp;                     /* tumour samples covered among U            */
+    int32_t fp;                     /* normal samples covered                    */
+    int32_t tn;                     /* n_normal - fp                             */
+    int32_t uncovered_before;       /* |U| at the start of the round             */
+    int64_t score_num;              /* S = p*tp + q*tn                           */
+    int64_t score_den;              /* q*(uncovered_before + n_normal); F = num/den */
+} pdfs_combo;
+
+/* Per-depth counters, index = depth (1..h), summed over rounds.
+ * visited[l]: depth-l nodes whose running intersection was formed (the loop
+ *   bounds of Alg. 2: depth l ranges over sorted indices up to G-h+l-1,
+ *   0-based); nonempty[l]: those with a non-empty tumour intersection;
+ *   bound_pruned[l]: non-empty prefixes dropped by the score bound.
+ * Under PDFS_PRUNE_EMPTY the counts are exact and order-independent.  Under
+ * PDFS_PRUNE_BOUND they depend on how fast the incumbent rises and are for
+ * information only. */
+typedef struct {
+    uint64_t visited[PDFS_MAX_H + 1];
+    uint64_t nonempty[PDFS_MAX_H + 1];
+    uint64_t bound_pruned[PDFS_MAX_H + 1];
+    int32_t rounds;
+    int32_t reserved;
+    int64_t ns_total;   /* host wall time of the call, nanoseconds */
+} pdfs_stats;
+
+/* Copies the cohort to the device, sorts genes sparsest first and sets up the
+ * round workspace.  *out receives the context (NULL on failure).  Errors:
+ * INVALID_ARG (shapes, strides, pad bits, n_tumor < 1, G < 1), OUT_OF_MEMORY,
+ * DEVICE. */
+int32_t pdfs_create(const pdfs_matrix *m, const pdfs_options *opt, pdfs_ctx **out);
+
+/* Releases the context and its device memory.  NULL is ignored. */
+void pdfs_destroy(pdfs_ctx *ctx);
+
+/* Changes the pruning mode of later calls. */
+int32_t pdfs_set_prune_mode(pdfs_ctx *ctx, int32_t prune_mode);
+
+/* One argmax round (step 4 of Alg. 1, done as Alg. 2): the best h-subset
+ * against the uncovered mask `uncovered` (host pointer, ceil(n_tumor/64)
+ * words, NULL = every tumour sample).  alpha = alpha_p / alpha_q with
+ * alpha_q >= 1.  Returns PDFS_OK with *out filled, PDFS_NO_COMBO when no
+ * subset has TP >= 1 (out->h = 0), or an error.  stats may be NULL; it is
+ * overwritten.  h: 1..4 on the GPU (UNSUPPORTED above). */
+int32_t pdfs_best_combo(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alpha_q,
+                        const uint64_t *uncovered, pdfs_combo *out, pdfs_stats *stats);
+
+/* The greedy weighted-set-cover loop (Alg. 1).  target_covered <= 0 means
+ * every tumour sample; max_rounds <= 0 means no cap.  initial_uncovered (host
+ * pointer, ceil(n_tumor/64) words) resumes from a previous state; NULL starts
+ * with every sample uncovered.  Rounds are written to out[0..cap); *n_out is
+ * the number of rounds.  If more than cap rounds were needed the call returns
+ * PDFS_ERR_TRUNCATED with *n_out = rounds needed (the first cap are written).
+ * final_uncovered (host, may be NULL) receives the mask after the last round.
+ * stats may be NULL. */
+int32_t pdfs_wsc_run(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alpha_q,
+                     int32_t target_covered, int32_t max_rounds,
+                     const uint64_t *initial_uncovered, pdfs_combo *out, int32_t cap,
+                     int32_t *n_out, uint64_t *final_uncovered, pdfs_stats *stats);
+
+const char *pdfs_strerror(int32_t status);
+const char *pdfs_last_error(const pdfs_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDFS_H */
