@@ -31,24 +31,33 @@ def build() -> str:
 _lib = None
 
 
+def load_library(path):
+    """Load an oracle build (the default one, or a test variant) with its signatures."""
+    L = ctypes.CDLL(path)
+    _declare(L)
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build()
-        L = ctypes.CDLL(LIB)
-        P = ctypes.c_void_p
-        i32, i64 = ctypes.c_int32, ctypes.c_int64
-        L.oracle_order.argtypes = [i32, i32, P, i32, P, P]
-        L.oracle_order.restype = None
-        L.oracle_best.argtypes = [i32, i32, i32, i32, P, i32, P, P, i32, i64, i64, P, i32,
-                                  P, P, P, P]
-        L.oracle_best.restype = ctypes.c_int
-        L.oracle_wsc.argtypes = [i32, i32, i32, i32, P, i32, P, i32, i64, i64, i32, i32, P,
-                                 i32, i32, P, P, P, P, P]
-        L.oracle_wsc.restype = ctypes.c_int
-        _lib = L
+        _lib = load_library(LIB)
     return _lib
+
+
+def _declare(L):
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    L.oracle_order.argtypes = [i32, i32, P, i32, P, P]
+    L.oracle_order.restype = None
+    L.oracle_best.argtypes = [i32, i32, i32, i32, P, i32, P, P, i32, i64, i64, P, i32,
+                              P, P, P, P]
+    L.oracle_best.restype = ctypes.c_int
+    L.oracle_wsc.argtypes = [i32, i32, i32, i32, P, i32, P, i32, i64, i64, i32, i32, P,
+                             i32, i32, P, P, P, P, P]
+    L.oracle_wsc.restype = ctypes.c_int
 
 
 def _ptr(a):
@@ -62,12 +71,12 @@ def _words(a):
     return a
 
 
-def order(T, N):
+def order(T, N, L=None):
     """Sorted (sparsest-first) position -> caller gene id."""
     T, N = _words(T), _words(N)
     G = T.shape[0]
     perm = np.zeros(G, dtype=np.int32)
-    lib().oracle_order(G, T.shape[1], _ptr(T), N.shape[1], _ptr(N), _ptr(perm))
+    (L or lib()).oracle_order(G, T.shape[1], _ptr(T), N.shape[1], _ptr(N), _ptr(perm))
     return perm
 
 
@@ -88,11 +97,11 @@ class Best:
     counters: dict
 
 
-def best(T, N, n_tumor, n_normal, h, p, q, U=None, mode="empty", perm=None) -> Best:
+def best(T, N, n_tumor, n_normal, h, p, q, U=None, mode="empty", perm=None, L=None) -> Best:
     T, N = _words(T), _words(N)
     G, wt = T.shape
     if perm is None:
-        perm = order(T, N)
+        perm = order(T, N, L)
     perm = np.ascontiguousarray(perm, dtype=np.int32)
     if U is None:
         U = full_mask(n_tumor, wt)
@@ -101,7 +110,7 @@ def best(T, N, n_tumor, n_normal, h, p, q, U=None, mode="empty", perm=None) -> B
     tp = np.zeros(1, dtype=np.int64)
     fp = np.zeros(1, dtype=np.int64)
     cnt = np.zeros(3 * (MAX_H + 1), dtype=np.uint64)
-    r = lib().oracle_best(G, n_tumor, n_normal, wt, _ptr(T), N.shape[1], _ptr(N), _ptr(perm),
+    r = (L or lib()).oracle_best(G, n_tumor, n_normal, wt, _ptr(T), N.shape[1], _ptr(N), _ptr(perm),
                           h, p, q, _ptr(U), MODES[mode], _ptr(idx), _ptr(tp), _ptr(fp),
                           _ptr(cnt))
     if r < 0:
@@ -129,7 +138,7 @@ class WscResult:
 
 
 def wsc(T, N, n_tumor, n_normal, h, p=1, q=10, target=0, max_rounds=0, U0=None,
-        mode="bound", cap=4096) -> WscResult:
+        mode="bound", cap=4096, L=None) -> WscResult:
     T, N = _words(T), _words(N)
     G, wt = T.shape
     genes = np.zeros(cap * h, dtype=np.int32)
@@ -138,7 +147,7 @@ def wsc(T, N, n_tumor, n_normal, h, p=1, q=10, target=0, max_rounds=0, U0=None,
     cnt = np.zeros(3 * (MAX_H + 1), dtype=np.uint64)
     Uo = np.zeros(wt, dtype=np.uint64)
     U0a = None if U0 is None else np.ascontiguousarray(U0, dtype=np.uint64)
-    r = lib().oracle_wsc(G, n_tumor, n_normal, wt, _ptr(T), N.shape[1], _ptr(N), h, p, q,
+    r = (L or lib()).oracle_wsc(G, n_tumor, n_normal, wt, _ptr(T), N.shape[1], _ptr(N), h, p, q,
                          target, max_rounds, _ptr(U0a), MODES[mode], cap, _ptr(genes),
                          _ptr(sidx), _ptr(rec), _ptr(cnt), _ptr(Uo))
     if r < 0:

@@ -1,0 +1,293 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test fixes the oracle's output from an independent source: the brute-
+force definition over all C(G,h) subsets, the paper's Table I, a plain
+matrix product (h=2), a closed form (h=1), the greedy loop's invariants,
+planted combinations in noise-free data, symmetries and resume.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bruteforce as bf
+from oracle import cpu
+from paper_2603_16721_amd import synth
+from tests.helpers import bits_of_mask, mask_of_bits, recount
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+TINY_CASES = [
+    # seed, G, n_tumor, n_normal, density, h, (p, q)
+    (1, 12, 70, 30, 0.30, 3, (1, 10)),
+    (2, 14, 64, 20, 0.35, 2, (1, 10)),
+    (3, 10, 130, 65, 0.40, 4, (1, 10)),
+    (4, 13, 40, 0, 0.30, 3, (1, 1)),
+    (5, 9, 100, 64, 0.50, 4, (3, 7)),
+    (6, 16, 90, 40, 0.25, 2, (0, 1)),
+    (7, 11, 65, 128, 0.45, 3, (1, 10)),
+    (8, 8, 128, 1, 0.50, 1, (1, 10)),
+    (9, 12, 200, 70, 0.35, 4, (1, 10)),
+    (10, 7, 33, 17, 0.6, 5, (2, 3)),
+]
+
+
+def _tiny(case):
+    seed, G, nt, nn, d, h, a = case
+    return synth.random_tiny(seed, G, nt, nn, d, h, alpha=a)
+
+
+@pytest.mark.parametrize("case", TINY_CASES)
+@pytest.mark.parametrize("mode", ["none", "empty", "bound"])
+def test_best_matches_bruteforce(case, mode):
+    """P-DFS never loses the optimum: one round equals the brute-force argmax
+    (Alg. 2 vs the plain definition), in all three pruning modes."""
+    I = _tiny(case)
+    T, N = I.packed()
+    rng = np.random.default_rng(case[0])
+    for trial in range(3):
+        unc = np.ones(I.n_tumor, bool) if trial == 0 else rng.random(I.n_tumor) < 0.6
+        b = cpu.best(T, N, I.n_tumor, I.n_normal, I.h, I.alpha_p, I.alpha_q,
+                     U=mask_of_bits(unc), mode=mode)
+        ref = bf.best(I.tumor, I.normal, I.h, I.alpha_p, I.alpha_q, unc)
+        if ref is None:
+            assert not b.found
+            continue
+        assert b.found
+        assert b.sorted_idx == ref[0]
+        assert (b.tp, b.fp, b.score) == (ref[1], ref[2], ref[3])
+
+
+@pytest.mark.parametrize("case", TINY_CASES)
+def test_wsc_matches_bruteforce(case):
+    """The whole greedy loop (Alg. 1) equals brute-force rounds."""
+    I = _tiny(case)
+    T, N = I.packed()
+    for mode in ("empty", "bound"):
+        r = cpu.wsc(T, N, I.n_tumor, I.n_normal, I.h, I.alpha_p, I.alpha_q, mode=mode)
+        ref = bf.wsc(I.tumor, I.normal, I.h, I.alpha_p, I.alpha_q)
+        assert len(r.rounds) == len(ref)
+        for a, b in zip(r.rounds, ref):
+            assert a["genes"] == b["genes"] and a["sorted_idx"] == b["sorted_idx"]
+            assert (a["tp"], a["fp"], a["score_num"]) == (b["tp"], b["fp"], b["score_num"])
+
+
+@pytest.mark.parametrize("case", TINY_CASES[:7])
+def test_empty_counters_match_enumeration(case):
+    """Per-depth visited / non-empty counts of the EMPTY walk equal a direct
+    enumeration of all l-tuples within Alg. 2's loop bounds."""
+    I = _tiny(case)
+    T, N = I.packed()
+    unc = np.random.default_rng(99).random(I.n_tumor) < 0.7
+    b = cpu.best(T, N, I.n_tumor, I.n_normal, I.h, I.alpha_p, I.alpha_q,
+                 U=mask_of_bits(unc), mode="empty")
+    vis, ne = bf.counts(I.tumor, I.normal, I.h, unc)
+    assert b.counters["visited"][1:I.h + 1] == vis[1:]
+    assert b.counters["nonempty"][1:I.h + 1] == ne[1:]
+
+
+def _table1():
+    vals = {}
+    with open(os.path.join(HERE, "golden", "table1_comb_growth.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                h, v = line.split()
+                vals[int(h)] = float(v)
+    return vals
+
+
+def test_table1_closed_form():
+    """C(20000,h) for h=2..9, truncated to three significant digits, equals
+    the paper's Table I (the table truncates: C(20000,2) = 199,990,000 is
+    printed as 1.99e8)."""
+    for h, v in _table1().items():
+        exact = math.comb(20000, h)
+        e = len(str(exact)) - 1
+        mant = exact // 10 ** (e - 2)            # first three digits
+        assert f"{mant / 100:.2f}e{e}" == f"{v:.2e}".replace("e+", "e").replace("e0", "e"), (h, exact, v)
+
+
+@pytest.mark.parametrize("G,h", [(9, 1), (10, 2), (11, 3), (12, 4), (10, 5)])
+def test_exhaustive_visits_all_subsets(G, h):
+    """The pruning-off baseline visits exactly C(G,h) leaves (the quantity of
+    Table I), and C(G,l)-style counts at inner depths."""
+    I = synth.random_tiny(G, G, 50, 20, 0.05, h)
+    T, N = I.packed()
+    b = cpu.best(T, N, I.n_tumor, I.n_normal, h, 1, 10, mode="none")
+    assert b.counters["visited"][h] == math.comb(G, h)
+    for l in range(1, h + 1):
+        # depth-l nodes: l-tuples whose last index leaves room for h-l more genes
+        expect = sum(1 for c in itertools.combinations(range(G), l)
+                     if all(c[j] <= G - h + j for j in range(l)))
+        assert b.counters["visited"][l] == expect
+
+
+def _pair_argmax(tumor, normal, unc, p, q):
+    """h=2 from a plain integer matrix product: TP = T_U T_U^T, FP = N N^T."""
+    order = bf.sparse_first_order(tumor, normal)
+    Tu = tumor[order][:, unc].astype(np.int64)
+    Ns = normal[order].astype(np.int64)
+    TP = Tu @ Tu.T
+    FP = Ns @ Ns.T
+    S = p * TP + q * (normal.shape[1] - FP)
+    G = tumor.shape[0]
+    iu = np.triu_indices(G, 1)
+    ok = TP[iu] > 0
+    if not ok.any():
+        return None
+    cand_s = S[iu][ok]
+    smax = cand_s.max()
+    a = iu[0][ok][cand_s == smax]
+    b = iu[1][ok][cand_s == smax]
+    k = np.lexsort((b, a))[0]
+    return (int(a[k]), int(b[k])), int(TP[a[k], b[k]]), int(FP[a[k], b[k]]), int(smax)
+
+
+def test_h2_equals_matrix_product_whole_wsc():
+    """Every round of the h=2 workload (G=500) equals the argmax of a plain
+    integer Gram matrix (the pairwise co-occurrence table)."""
+    I = synth.workload_small_h2()
+    T, N = I.packed()
+    r = cpu.wsc(T, N, I.n_tumor, I.n_normal, 2, 1, 10, mode="empty")
+    unc = np.ones(I.n_tumor, bool)
+    assert len(r.rounds) > 10
+    for rd in r.rounds:
+        ref = _pair_argmax(I.tumor, I.normal, unc, 1, 10)
+        assert tuple(rd["sorted_idx"]) == ref[0]
+        assert (rd["tp"], rd["fp"], rd["score_num"]) == ref[1:]
+        unc &= ~np.all(I.tumor[rd["genes"]], axis=0)
+    assert _pair_argmax(I.tumor, I.normal, unc, 1, 10) is None
+
+
+def test_h1_closed_form():
+    """h=1: argmax over genes of p*|T_g & U| + q*(N_n - |N_g|)."""
+    I = synth.workload_small_h2()
+    T, N = I.packed()
+    order = bf.sparse_first_order(I.tumor, I.normal)
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        unc = rng.random(I.n_tumor) < 0.5
+        tp = I.tumor[order][:, unc].sum(1)
+        fp = I.normal[order].sum(1)
+        S = np.where(tp > 0, 1 * tp + 10 * (I.n_normal - fp), -1)
+        i = int(np.argmax(S))  # first maximum = smallest sorted index
+        b = cpu.best(T, N, I.n_tumor, I.n_normal, 1, 1, 10, U=mask_of_bits(unc))
+        assert b.sorted_idx == (i,) and b.score == S[i]
+
+
+def _check_invariants(I, rounds, final_unc, h, p, q, full_rule):
+    unc = np.ones(I.n_tumor, bool)
+    prev_s = None
+    seen = set()
+    for rd in rounds:
+        tp, fp, cov = recount(I.tumor, I.normal, rd["genes"], unc)
+        assert (tp, fp) == (rd["tp"], rd["fp"])             # recount from raw bits
+        assert tp >= 1
+        assert rd["tn"] == I.n_normal - fp
+        assert rd["score_num"] == p * tp + q * (I.n_normal - fp)
+        assert rd["uncovered_before"] == unc.sum()
+        assert rd["score_den"] == q * (unc.sum() + I.n_normal)
+        if p <= q:
+            assert 0 <= rd["score_num"] <= rd["score_den"]    # 0 <= F <= 1
+        if prev_s is not None:
+            assert rd["score_num"] <= prev_s                  # S*_{r+1} <= S*_r
+        prev_s = rd["score_num"]
+        key = tuple(sorted(rd["genes"]))
+        assert key not in seen
+        seen.add(key)
+        new_unc = unc & ~cov
+        assert new_unc.sum() == unc.sum() - tp                # strictly growing cover
+        unc = new_unc
+    assert np.array_equal(unc, bits_of_mask(final_unc, I.n_tumor))
+    if full_rule:
+        # stop only when no h genes share an uncovered tumour sample
+        per_sample = I.tumor[:, unc].sum(0)
+        assert np.all(per_sample < h)
+
+
+def test_invariants_h2_workload():
+    I = synth.workload_small_h2()
+    T, N = I.packed()
+    r = cpu.wsc(T, N, I.n_tumor, I.n_normal, 2, 1, 10, mode="bound")
+    _check_invariants(I, r.rounds, r.final_uncovered, 2, 1, 10, True)
+
+
+def test_invariants_h3_workload():
+    I = synth.workload_h3_g5000()
+    T, N = I.packed()
+    r = cpu.wsc(T, N, I.n_tumor, I.n_normal, 3, 1, 10, target=I.target_covered, mode="bound")
+    _check_invariants(I, r.rounds, r.final_uncovered, 3, 1, 10, False)
+    covered = I.n_tumor - bits_of_mask(r.final_uncovered, I.n_tumor).sum()
+    assert covered >= I.target_covered
+
+
+@pytest.mark.parametrize("case", TINY_CASES)
+def test_invariants_tiny(case):
+    I = _tiny(case)
+    T, N = I.packed()
+    r = cpu.wsc(T, N, I.n_tumor, I.n_normal, I.h, I.alpha_p, I.alpha_q, mode="bound")
+    _check_invariants(I, r.rounds, r.final_uncovered, I.h, I.alpha_p, I.alpha_q, True)
+
+
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_planted_recovery_noise_free(h):
+    """Only planted bits, no normals: round r picks the planted combination
+    with the r-th largest sample count (ties to the smaller sorted tuple)."""
+    rng = np.random.Generator(np.random.PCG64(1234 + h))
+    sizes = [9, 14, 5, 14, 11, 3]
+    I = synth.make_instance("planted", rng, 60, 80, 30, h, np.zeros(60), len(sizes), sizes)
+    T, N = I.packed()
+    order = list(bf.sparse_first_order(I.tumor, I.normal))
+    pos = {g: i for i, g in enumerate(order)}
+    expect = sorted(((len(s), tuple(sorted(pos[g] for g in genes))) for genes, s in I.planted),
+                    key=lambda x: (-x[0], x[1]))
+    r = cpu.wsc(T, N, I.n_tumor, I.n_normal, h, 1, 10, mode="bound")
+    assert [(rd["tp"], tuple(rd["sorted_idx"])) for rd in r.rounds] == expect
+
+
+def test_symmetry_sample_and_gene_permutations():
+    """Permuting sample columns changes nothing; permuting gene rows (the
+    sort keys here are unique after the tie-break on caller id, so we permute
+    within a fixed sorted order by relabelling) maps ids and nothing else."""
+    I = _tiny((11, 12, 90, 40, 0.35, 3, (1, 10)))
+    T, N = I.packed()
+    base = cpu.wsc(T, N, I.n_tumor, I.n_normal, 3, 1, 10, mode="empty")
+    rng = np.random.default_rng(3)
+    ps = rng.permutation(I.n_tumor)
+    pn = rng.permutation(I.n_normal)
+    T2, N2 = synth.pack_rows(I.tumor[:, ps]), synth.pack_rows(I.normal[:, pn])
+    r2 = cpu.wsc(T2, N2, I.n_tumor, I.n_normal, 3, 1, 10, mode="empty")
+    assert [x["genes"] for x in r2.rounds] == [x["genes"] for x in base.rounds]
+    assert [x["score_num"] for x in r2.rounds] == [x["score_num"] for x in base.rounds]
+    # gene relabelling that keeps every (count, id) comparison: reverse ids of
+    # genes with distinct counts is not order-preserving in general, so use a
+    # relabelling that is monotone (shift ids by inserting empty genes).
+    G = I.G
+    pad = np.zeros((3, I.n_tumor), bool), np.zeros((3, I.n_normal), bool)
+    T3 = synth.pack_rows(np.vstack([pad[0], I.tumor]))
+    N3 = synth.pack_rows(np.vstack([pad[1], I.normal]))
+    r3 = cpu.wsc(T3, N3, I.n_tumor, I.n_normal, 3, 1, 10, mode="empty")
+    assert [[g - 3 for g in x["genes"]] for x in r3.rounds] == [x["genes"] for x in base.rounds]
+    assert G == T.shape[0]
+
+
+def test_resume_equals_straight_run():
+    I = synth.workload_small_h2()
+    T, N = I.packed()
+    full = cpu.wsc(T, N, I.n_tumor, I.n_normal, 2, 1, 10, mode="bound")
+    part = cpu.wsc(T, N, I.n_tumor, I.n_normal, 2, 1, 10, max_rounds=7, mode="bound")
+    rest = cpu.wsc(T, N, I.n_tumor, I.n_normal, 2, 1, 10, U0=part.final_uncovered, mode="bound")
+    joined = part.rounds + rest.rounds
+    assert [x["genes"] for x in joined] == [x["genes"] for x in full.rounds]
+    assert np.array_equal(rest.final_uncovered, full.final_uncovered)
+
+
+def test_modes_identical_h3_workload_first_rounds():
+    """EMPTY (the paper's Alg. 2) and BOUND return the same rounds."""
+    I = synth.workload_h3_g5000()
+    T, N = I.packed()
+    e = cpu.wsc(T, N, I.n_tumor, I.n_normal, 3, 1, 10, max_rounds=2, mode="empty")
+    b = cpu.wsc(T, N, I.n_tumor, I.n_normal, 3, 1, 10, max_rounds=2, mode="bound")
+    assert e.rounds == b.rounds
