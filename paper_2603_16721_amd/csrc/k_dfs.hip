@@ -1,0 +1,470 @@
+// Depth-first expansion of the non-empty pairs (Alg. 2 depths 3..h, h <= 4).
+//
+// Work unit (the lambda subtree of Sec. III-D, batched): 64 consecutive
+// non-empty pairs (one per lane) x a contiguous range of depth-3 candidates.
+// Ranges are cut into chunks so that waves pulling items from one atomic
+// cursor stay balanced (the paper hands out fixed-size lambda intervals on
+// request for the same reason).
+//
+// Inner loop: each lane keeps its prefix intersection y (and the normal
+// prefix z) in VGPRs; the wave walks candidates c in ascending order, the
+// candidate row arrives through scalar loads (one copy for all 64 lanes) and
+// every lane folds y & row into an emptiness test with v_and_or_b32.  A lane
+// whose y_l & row is empty backtracks (Alg. 2: the prefix is not extended).
+//
+// h = 3: a non-empty y3 is a leaf, scored at once.
+// h = 4: a non-empty (lane, c) is a depth-3 prefix; it is staged in an LDS
+//   queue in ascending c.  Each full queue of 64 prefixes becomes a depth-4
+//   pass with one prefix per lane (y3 = y2[s] & T_c built with cross-lane
+//   permutes), again streaming candidates d > c through scalar loads; a
+//   non-empty y4 is a leaf.
+//
+// Leaves: TP = |y_h| (popcount), FP = |z_{h-1} & N_g| (skipped when the
+// normal prefix is already empty), S = p*TP + q*(N_n - FP); each lane keeps
+// the best (S desc, tuple asc), reduced per wave into a slot.
+//
+// Bound mode (Sec. III-E, exact): a prefix covering c uncovered samples
+// cannot score above p*c + q*N_n.  The best leaf found so far is kept in one
+// 64-bit atomic key (S+1)<<32 | (0xffff-a)<<16 | (0xffff-b) (a, b = first two
+// indices); a prefix is dropped when its bound is below that score, or equal
+// to it with first two indices lexicographically above the key's -- then
+// every tuple under it loses to a tuple already found.
+#include "pdfs_dev.h"
+
+namespace pdfs {
+
+namespace {
+
+constexpr int kChunk = 256;
+
+// Read-only view of the round's rows.  The rows do not change while a DFS
+// kernel runs, so reading them through the constant address space lets the
+// compiler fetch a wave-uniform row with scalar loads (one copy per wave,
+// held in SGPRs, used directly as VALU operands).
+typedef const __attribute__((address_space(4))) uint32_t cu32;
+
+// d = (a & b) | c with b a wave-uniform (SGPR) operand.
+__device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+  return d;
+}
+
+// acc + popcount(x)
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+  uint32_t d;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(d) : "v"(x), "v"(acc));
+  return d;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// OR over k of (y[k] & row[k]) with four independent chains.
+template <int W>
+__device__ __forceinline__ uint32_t fold_nonempty(const uint32_t (&y)[W], cu32* row) {
+  uint32_t r[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) r[k] = row[k];
+  uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+  for (int k = 0; k < W; k += 4) {
+    a0 = and_or(y[k], r[k], a0);
+    if (k + 1 < W) a1 = and_or(y[k + 1], r[k + 1], a1);
+    if (k + 2 < W) a2 = and_or(y[k + 2], r[k + 2], a2);
+    if (k + 3 < W) a3 = and_or(y[k + 3], r[k + 3], a3);
+  }
+  return a0 | a1 | a2 | a3;
+}
+
+// sum over k of popcount(y[k] & row[k]), four accumulator chains.
+template <int W>
+__device__ __forceinline__ int popc_and(const uint32_t (&y)[W], cu32* row) {
+  uint32_t r[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) r[k] = row[k];
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+#pragma unroll
+  for (int k = 0; k < W; k += 4) {
+    c0 = bcnt_acc(y[k] & r[k], c0);
+    if (k + 1 < W) c1 = bcnt_acc(y[k + 1] & r[k + 1], c1);
+    if (k + 2 < W) c2 = bcnt_acc(y[k + 2] & r[k + 2], c2);
+    if (k + 3 < W) c3 = bcnt_acc(y[k + 3] & r[k + 3], c3);
+  }
+  return (int)(c0 + c1 + c2 + c3);
+}
+
+__device__ __forceinline__ int popc_and_n(const uint32_t (&z)[kMaxWN32], cu32* row) {
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxWN32; ++k) c += __popc(z[k] & row[k]);
+  return c;
+}
+
+__device__ __forceinline__ unsigned long long load_incumbent(RoundState* st) {
+  return __hip_atomic_load(&st->incumbent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// true when a prefix with first indices (a, b) and score bound ub cannot
+// produce the round's answer.
+__device__ __forceinline__ bool dominated(int ub, int a, int b, unsigned long long inc) {
+  if (inc == 0) return false;
+  const int s = (int)(inc >> 32) - 1;
+  if (ub != s) return ub < s;
+  const int g1 = 0xffff - (int)((inc >> 16) & 0xffff);
+  const int g2 = 0xffff - (int)(inc & 0xffff);
+  return a > g1 || (a == g1 && b > g2);
+}
+
+__device__ __forceinline__ unsigned long long leaf_key(int s, int a, int b) {
+  return ((unsigned long long)(s + 1) << 32) | ((unsigned long long)(0xffff - a) << 16) |
+         (unsigned long long)(0xffff - b);
+}
+
+// Orders this wave's LDS writes before its later LDS reads of other lanes'
+// entries.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct Best {
+  int s, tp, fp;
+  int i0, i1, i2, i3;
+  __device__ void init() { s = -1; tp = fp = 0; i0 = i1 = i2 = i3 = 0; }
+  __device__ bool beaten_by(int s2, int j0, int j1, int j2, int j3) const {
+    if (s2 != s) return s2 > s;
+    if (j0 != i0) return j0 < i0;
+    if (j1 != i1) return j1 < i1;
+    if (j2 != i2) return j2 < i2;
+    return j3 < i3;
+  }
+  __device__ void offer(int s2, int tp2, int fp2, int j0, int j1, int j2, int j3) {
+    if (beaten_by(s2, j0, j1, j2, j3)) { s = s2; tp = tp2; fp = fp2; i0 = j0; i1 = j1; i2 = j2; i3 = j3; }
+  }
+};
+
+struct Tally {
+  unsigned long long ne3, ne4, vis3, vis4, bp2, bp3;
+  __device__ void init() { ne3 = ne4 = vis3 = vis4 = bp2 = bp3 = 0; }
+};
+
+// Depth-4 pass over n <= 64 staged prefixes (queue entries lane | c << 6,
+// ascending c).
+template <int W>
+__device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundState* st,
+                                       const uint32_t* q, int n, const uint32_t (&y2)[W],
+                                       const uint32_t (&z2)[kMaxWN32], int a, int b, Best& best,
+                                       Tally& tl, unsigned long long& inc, int lane) {
+  const int nA = uniform(st->nA);
+  const bool valid = lane < n;
+  const uint32_t e = q[valid ? lane : 0];
+  const int s = e & 63;
+  const int c = (int)(e >> 6);
+  cu32* TA = (cu32*)w.TA;
+  cu32* NA = (cu32*)w.NA;
+  uint32_t y3[W];
+  uint32_t z3[kMaxWN32];
+  const uint32_t vmask = valid ? ~0u : 0u;
+  const int cc = valid ? c : 0;   // any in-range row for idle lanes
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    uint32_t v = __shfl(y2[k], s, 64);
+    y3[k] = v & TA[(size_t)cc * W + k] & vmask;
+  }
+  uint32_t znz = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxWN32; ++k) {
+    uint32_t v = __shfl(z2[k], s, 64);
+    z3[k] = v & NA[(size_t)cc * kMaxWN32 + k] & vmask;
+    znz |= z3[k];
+  }
+  const int a3 = __shfl(a, s, 64);
+  const int b3 = __shfl(b, s, 64);
+  const int c_first = uniform((int)(q[0] >> 6));
+  bool live = valid;
+  if (P.mode == kPruneBound) {
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) cnt += __popc(y3[k]);
+    inc = load_incumbent(st);
+    const bool drop = live && dominated(P.p * cnt + P.q * P.n_normal, a3, b3, inc);
+    tl.bp3 += __popcll(__ballot(drop));
+    live = live && !drop;
+    if (!__any(live)) return;
+  }
+  const bool zlive = live && znz != 0;
+  for (int d = c_first + 1; d < nA; ++d) {
+    cu32* row = TA + (size_t)d * W;
+    const int tp = popc_and<W>(y3, row);
+    const bool hit = live && d > c && tp > 0;
+    const unsigned long long m = __ballot(hit);
+    if (m == 0) continue;
+    tl.ne4 += __popcll(m);
+    int fp = 0;
+    if (__any(hit && zlive)) {
+      if (hit && zlive) fp = popc_and_n(z3, NA + (size_t)d * kMaxWN32);
+    }
+    if (hit) {
+      const int sc = P.p * tp + P.q * (P.n_normal - fp);
+      best.offer(sc, tp, fp, a3, b3, c, d);
+      if (P.mode == kPruneBound) {
+        const unsigned long long key = leaf_key(sc, a3, b3);
+        if (key > inc) {
+          const unsigned long long old = atomicMax(&st->incumbent, key);
+          inc = old > key ? old : key;
+        }
+      }
+    }
+  }
+}
+
+template <int H, int W64>
+__global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
+  constexpr int W = 2 * W64;
+  __shared__ uint32_t qbuf[kBlock / kWave][2 * kWave];
+  RoundState* st = w.st;
+  const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
+  const int gw = blockIdx.x * (kBlock / kWave) + wib;
+  uint32_t* q = qbuf[wib];
+  const unsigned long long npairs = st->n_work_pairs;
+  const uint32_t nitems = (uint32_t)uniform((int)st->n_items);
+  const __attribute__((address_space(4))) Item* items =
+      (const __attribute__((address_space(4))) Item*)w.items;
+  cu32* TA = (cu32*)w.TA;
+  cu32* NA = (cu32*)w.NA;
+
+  Best best;
+  best.init();
+  Tally tl;
+  tl.init();
+  unsigned long long inc = 0;
+
+  for (;;) {
+    uint32_t it = 0;
+    if (lane == 0) it = (uint32_t)atomicAdd(&st->cursor, 1ull);
+    it = (uint32_t)uniform((int)it);
+    if (it >= nitems) break;
+    const int c_lo = uniform((int)items[it].c_lo);
+    const int c_hi = uniform((int)items[it].c_hi);
+    const uint32_t batch = (uint32_t)uniform((int)items[it].batch);
+    const uint32_t first_chunk = (uint32_t)uniform((int)items[it].pad) & 1u;
+    const unsigned long long pi = (unsigned long long)batch * kPairBatch + lane;
+    bool valid = pi < npairs;
+    const unsigned long long e = valid ? w.work_pairs[pi] : 0ull;
+    const int a = (int)(e & 0xffff);
+    const int b = (int)((e >> 16) & 0xffff);
+    const int ct = (int)((e >> 32) & 0xffff);
+    if (P.mode == kPruneBound) {
+      inc = load_incumbent(st);
+      const bool drop = valid && dominated(P.p * ct + P.q * P.n_normal, a, b, inc);
+      if (first_chunk) {
+        tl.bp2 += __popcll(__ballot(drop));
+        if (valid && !drop) tl.vis3 += (unsigned long long)(P.G - H + 2 - w.act[b]);
+      }
+      valid = valid && !drop;
+    }
+    if (!__any(valid)) continue;
+    uint32_t y2[W];
+    uint32_t z2[kMaxWN32];
+    const uint32_t vmask = valid ? ~0u : 0u;
+    const int ra = valid ? a : 0, rb = valid ? b : 0;   // in-range rows for idle lanes
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+      y2[k] = TA[(size_t)ra * W + k] & TA[(size_t)rb * W + k] & vmask;
+#pragma unroll
+    for (int k = 0; k < kMaxWN32; ++k)
+      z2[k] = NA[(size_t)ra * kMaxWN32 + k] & NA[(size_t)rb * kMaxWN32 + k] & vmask;
+    uint32_t znz = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxWN32; ++k) znz |= z2[k];
+
+    int qn = 0;
+    for (int c = c_lo; c < c_hi; ++c) {
+      cu32* row = TA + (size_t)c * W;
+      const uint32_t acc = fold_nonempty<W>(y2, row);
+      bool hit = valid && c > b && acc != 0;
+      unsigned long long m = __ballot(hit);
+      if (m == 0) continue;
+      tl.ne3 += __popcll(m);
+      if (H == 3) {
+        int fp = 0;
+        if (__any(hit && znz != 0)) {
+          if (hit && znz != 0) fp = popc_and_n(z2, NA + (size_t)c * kMaxWN32);
+        }
+        if (hit) {
+          const int tp = popc_and<W>(y2, row);
+          const int sc = P.p * tp + P.q * (P.n_normal - fp);
+          best.offer(sc, tp, fp, a, b, c, 0);
+          if (P.mode == kPruneBound) {
+            const unsigned long long key = leaf_key(sc, a, b);
+            if (key > inc) {
+              const unsigned long long old = atomicMax(&st->incumbent, key);
+              inc = old > key ? old : key;
+            }
+          }
+        }
+      } else {
+        if (P.mode == kPruneBound) {
+          bool drop = false;
+          if (hit) {
+            const int cnt = popc_and<W>(y2, row);
+            drop = dominated(P.p * cnt + P.q * P.n_normal, a, b, inc);
+          }
+          tl.bp3 += __popcll(__ballot(drop));
+          hit = hit && !drop;
+          m = __ballot(hit);
+          if (m == 0) continue;
+        }
+        // visited at depth 4 for each extended triple: sorted indices in
+        // (idx(c), G-1]
+        tl.vis4 += (unsigned long long)__popcll(m) * (unsigned long long)(P.G - 1 - uniform(w.act[c]));
+        const int pos = qn + __popcll(m & ((1ull << lane) - 1));
+        if (hit) q[pos] = (uint32_t)lane | ((uint32_t)c << 6);
+        qn += __popcll(m);
+        wave_lds_sync();
+        if (qn >= kWave) {
+          depth4<W>(P, w, st, q, kWave, y2, z2, a, b, best, tl, inc, lane);
+          const int rest = qn - kWave;
+          const uint32_t moved = (lane < rest) ? q[kWave + lane] : 0u;
+          wave_lds_sync();
+          if (lane < rest) q[lane] = moved;
+          wave_lds_sync();
+          qn = rest;
+        }
+      }
+    }
+    if (H == 4 && qn > 0) {
+      depth4<W>(P, w, st, q, qn, y2, z2, a, b, best, tl, inc, lane);
+      qn = 0;
+    }
+  }
+
+  // wave argmax -> slot
+  for (int o = 32; o > 0; o >>= 1) {
+    const int s2 = __shfl_xor(best.s, o, 64), tp2 = __shfl_xor(best.tp, o, 64);
+    const int fp2 = __shfl_xor(best.fp, o, 64);
+    const int j0 = __shfl_xor(best.i0, o, 64), j1 = __shfl_xor(best.i1, o, 64);
+    const int j2 = __shfl_xor(best.i2, o, 64), j3 = __shfl_xor(best.i3, o, 64);
+    if (s2 >= 0) best.offer(s2, tp2, fp2, j0, j1, j2, j3);
+  }
+  if (lane == 0) {
+    Slot sl;
+    sl.s = best.s; sl.tp = best.tp; sl.fp = best.fp;
+    sl.idx[0] = best.i0; sl.idx[1] = best.i1; sl.idx[2] = best.i2; sl.idx[3] = best.i3;
+    sl.pad = 0;
+    w.slots[(size_t)phase * kSlotsPerPhase + gw] = sl;
+    if (tl.ne3) atomicAdd(&st->cnt.nonempty[3], tl.ne3);
+    if (H == 4 && tl.ne4) atomicAdd(&st->cnt.nonempty[4], tl.ne4);
+    if (H == 4 && tl.vis4) atomicAdd(&st->cnt.visited[4], tl.vis4);
+    if (tl.vis3) atomicAdd(&st->cnt.visited[3], tl.vis3);
+    if (tl.bp2) atomicAdd(&st->cnt.bound_pruned[2], tl.bp2);
+    if (tl.bp3) atomicAdd(&st->cnt.bound_pruned[3], tl.bp3);
+  }
+}
+
+// One wave per batch of kPairBatch work pairs: the batch's depth-3 candidate
+// range (min b + 1 .. amax[3]) cut into chunks.
+__global__ __launch_bounds__(256) void k_make_items(Problem P, Work w) {
+  RoundState* st = w.st;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const unsigned long long np = st->n_work_pairs;
+  const unsigned long long nb = (np + kPairBatch - 1) / kPairBatch;
+  const int amax3 = st->amax[3];
+  // chunk length so that the item list cannot overflow
+  unsigned long long chunk = kChunk;
+  const unsigned long long room = w.item_cap > nb ? w.item_cap - nb : 1;
+  const unsigned long long need = (nb * (unsigned long long)st->nA + room - 1) / room;
+  if (need > chunk) chunk = need;
+  for (unsigned long long bi = gw; bi < nb; bi += kWavesPerGrid) {
+    const unsigned long long pi = bi * kPairBatch + lane;
+    int b = 0x7fffffff;
+    if (pi < np) b = (int)((w.work_pairs[pi] >> 16) & 0xffff);
+    for (int o = 32; o > 0; o >>= 1) b = min(b, __shfl_xor(b, o, 64));
+    const int lo = b + 1, hi = amax3;
+    if (lo >= hi) continue;
+    const unsigned long long len = (unsigned long long)(hi - lo);
+    const unsigned long long n = (len + chunk - 1) / chunk;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&st->n_items, n);
+    base = __shfl(base, 0, 64);
+    for (unsigned long long k = lane; k < n; k += 64) {
+      if (base + k < w.item_cap) {
+        Item it;
+        it.batch = (uint32_t)bi;
+        it.c_lo = (uint32_t)(lo + k * chunk);
+        unsigned long long e = lo + (k + 1) * chunk;
+        it.c_hi = (uint32_t)(e < (unsigned long long)hi ? e : hi);
+        it.pad = (k == 0) ? 1u : 0u;
+        w.items[base + k] = it;
+      }
+    }
+  }
+}
+
+__global__ void k_clamp_items(Work w) {
+  RoundState* st = w.st;
+  if (st->n_items > w.item_cap) {
+    st->n_items = w.item_cap;
+    st->overflow = 1;
+  }
+  if (st->n_pairs > w.pair_cap) {
+    st->n_pairs = w.pair_cap;
+    st->overflow = 1;
+  }
+  st->cursor = 0;
+}
+
+__global__ void k_use_all_pairs(Work w) {
+  RoundState* st = w.st;
+  unsigned long long n = st->n_pairs;
+  if (n > w.pair_cap) { n = w.pair_cap; st->overflow = 1; }
+  st->n_pairs = n;
+  st->n_work_pairs = n;
+}
+
+template <int H>
+hipError_t dispatch(const Problem& P, const Work& w, int phase, hipStream_t s) {
+  dim3 g(kPersistBlocks), b(kBlock);
+  switch (w.w64) {
+#define PDFS_CASE(n) \
+  case n:            \
+    k_dfs<H, n><<<g, b, 0, s>>>(P, w, phase); break;
+    PDFS_CASE(1) PDFS_CASE(2) PDFS_CASE(3) PDFS_CASE(4) PDFS_CASE(5) PDFS_CASE(6)
+    PDFS_CASE(7) PDFS_CASE(8) PDFS_CASE(10) PDFS_CASE(12) PDFS_CASE(14) PDFS_CASE(16)
+    PDFS_CASE(18) PDFS_CASE(20)
+#undef PDFS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Row width (64-bit words) the DFS kernels are built for: the smallest
+// instantiated width that holds n words.
+int dfs_row_words(int n) {
+  static const int widths[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 18, 20};
+  for (int v : widths)
+    if (v >= n) return v;
+  return -1;
+}
+
+hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStream_t s) {
+  (void)seed;
+  k_use_all_pairs<<<1, 1, 0, s>>>(w);
+  k_make_items<<<kPersistBlocks, kBlock, 0, s>>>(P, w);
+  k_clamp_items<<<1, 1, 0, s>>>(w);
+  return hipGetLastError();
+}
+
+hipError_t launch_dfs(const Problem& P, const Work& w, int phase, hipStream_t s) {
+  if (P.h == 3) return dispatch<3>(P, w, phase, s);
+  if (P.h == 4) return dispatch<4>(P, w, phase, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace pdfs

@@ -1,0 +1,407 @@
+// Ingest and per-round kernels of the P-DFS / greedy-WSC path.
+//
+//  ingest (once per cohort, Sec. III-B): per-gene combined mutation counts,
+//    stable radix sort -> sparsest-first order, gather of the sorted rows.
+//  round begin / active / gather (Alg. 1 DelCols + Alg. 2 depth 1): the
+//    uncovered sample list, the genes whose row meets it (a gene whose
+//    depth-1 intersection is empty roots no combination with TP >= 1), and
+//    the active rows re-packed over the uncovered columns only, so every
+//    later intersection runs over ceil(|U|/64) words.
+//  finish (Alg. 1 steps 4-7): exact (S desc, tuple asc) argmax over the
+//    per-wave bests, the round record, and U <- U & ~cover(gamma*).
+#include <hipcub/hipcub.hpp>
+
+#include "pdfs_dev.h"
+
+namespace pdfs {
+
+namespace {
+
+__device__ __forceinline__ bool lex_less4(const int32_t* x, const int32_t* y, int h) {
+  for (int i = 0; i < h; ++i) {
+    if (x[i] != y[i]) return x[i] < y[i];
+  }
+  return false;
+}
+
+// ------------------------------------------------------------- ingest
+__global__ void k_gene_counts(const uint64_t* __restrict__ T, int64_t ts,
+                              const uint64_t* __restrict__ N, int64_t ns, int G, int wt, int wn,
+                              uint32_t* __restrict__ counts, int32_t* __restrict__ ids) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  uint32_t c = 0;
+  for (int w = 0; w < wt; ++w) c += __popcll(T[(size_t)g * ts + w]);
+  if (N)
+    for (int w = 0; w < wn; ++w) c += __popcll(N[(size_t)g * ns + w]);
+  counts[g] = c;
+  ids[g] = g;
+}
+
+__global__ void k_gather_sorted(const uint64_t* __restrict__ T, int64_t ts,
+                                const uint64_t* __restrict__ N, int64_t ns,
+                                const int32_t* __restrict__ perm, int G, int wt, int wn,
+                                uint64_t* __restrict__ Ts, uint64_t* __restrict__ Ns) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G) return;
+  int g = perm[i];
+  for (int w = 0; w < wt; ++w) Ts[(size_t)i * wt + w] = T[(size_t)g * ts + w];
+  for (int w = 0; w < wn; ++w) Ns[(size_t)i * wn + w] = N ? N[(size_t)g * ns + w] : 0ull;
+}
+
+__global__ void k_check_pad(const uint64_t* __restrict__ T, int64_t ts, int G, int n,
+                            int* __restrict__ bad) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G || (n & 63) == 0) return;
+  int last = n >> 6;
+  uint64_t pad = ~0ull << (n & 63);
+  if (T[(size_t)g * ts + last] & pad) atomicOr(bad, 1);
+}
+
+__global__ void k_fill_u(uint64_t* U, int wt, int n) {
+  int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= wt) return;
+  int lo = w * 64;
+  uint64_t v = 0;
+  if (n - lo >= 64) v = ~0ull;
+  else if (n > lo) v = (1ull << (n - lo)) - 1;
+  U[w] = v;
+}
+
+// ------------------------------------------------------------- round begin
+// One block of 64 threads: uncovered sample list and state reset.
+__global__ void k_round_begin(Problem P, Work w) {
+  RoundState* st = w.st;
+  const int lane = threadIdx.x;
+  int base = 0;
+  for (int w0 = 0; w0 < P.wt; w0 += 64) {
+    int wi = w0 + lane;
+    uint64_t word = wi < P.wt ? w.U[wi] : 0ull;
+    int c = __popcll(word);
+    int incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    int off = base + incl - c;
+    while (word) {
+      int bit = __ffsll((unsigned long long)word) - 1;
+      w.cols[off++] = wi * 64 + bit;
+      word &= word - 1;
+    }
+    base += __shfl(incl, 63, 64);
+  }
+  if (lane == 0) {
+    st->n_unc = base;
+    st->nA = 0;
+    st->found = 0;
+    st->n_pairs = 0;
+    st->n_work_pairs = 0;
+    st->n_items = 0;
+    st->cursor = 0;
+    st->incumbent = 0;
+    st->seed_n = 0;
+    st->overflow = 0;
+  }
+  for (int l = lane; l <= kMaxH; l += 64) {
+    st->amax[l] = 0;
+    st->cnt.visited[l] = 0;
+    st->cnt.nonempty[l] = 0;
+    st->cnt.bound_pruned[l] = 0;
+  }
+}
+
+// ------------------------------------------------------------- active genes
+__global__ void k_active_flags(Problem P, Work w) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= P.G) return;
+  uint64_t acc = 0;
+  const uint64_t* row = w.Ts + (size_t)g * P.wt;
+  for (int k = 0; k < P.wt; ++k) acc |= row[k] & w.U[k];
+  w.flags[g] = acc != 0;
+}
+
+// One block of 1024 threads: ordered compaction of the active flags, the
+// per-depth limits amax[l] and the depth-1/2 counters (Alg. 2 loop bounds:
+// depth l takes sorted indices up to G-h+l-1).
+__global__ __launch_bounds__(1024) void k_active_scan(Problem P, Work w) {
+  __shared__ int wsum[16];
+  __shared__ unsigned long long vsum[16];
+  RoundState* st = w.st;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int h = P.h;
+  int base = 0;
+  unsigned long long vis2 = 0;
+  for (int g0 = 0; g0 < P.G; g0 += 1024) {
+    int g = g0 + tid;
+    int f = (g < P.G) ? w.flags[g] : 0;
+    unsigned long long m = __ballot(f);
+    int pre = __popcll(m & ((1ull << lane) - 1));
+    if (lane == 0) wsum[wid] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < 16; ++i) {
+      off += (i < wid) ? wsum[i] : 0;
+      tot += wsum[i];
+    }
+    if (f) {
+      w.act[base + off + pre] = g;
+      if (h >= 2 && g <= P.G - h) vis2 += (unsigned long long)(P.G - h + 1 - g);
+    }
+    base += tot;
+    __syncthreads();
+  }
+  for (int o = 32; o > 0; o >>= 1) vis2 += __shfl_xor(vis2, o, 64);
+  if (lane == 0) vsum[wid] = vis2;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long v = 0;
+    for (int i = 0; i < 16; ++i) v += vsum[i];
+    st->nA = base;
+    st->cnt.visited[1] = (unsigned long long)(P.G - h + 1);
+    if (h >= 2) st->cnt.visited[2] = v;
+  }
+  // amax[l] = number of active genes with sorted index <= G-h+l-1.  act is
+  // ascending, so it is a binary search per depth.
+  if (tid >= 1 && tid <= h) {
+    int lim = P.G - h + tid - 1;
+    int lo = 0, hi = base;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (w.act[mid] <= lim) lo = mid + 1; else hi = mid;
+    }
+    st->amax[tid] = lo;
+    if (tid == 1) st->cnt.nonempty[1] = (unsigned long long)lo;
+  }
+}
+
+// One wave per active gene: the row over the uncovered columns (the paper's
+// DelCols done physically), the normal row, and optionally 0/1 bytes for the
+// int8 MFMA pair table.
+__global__ __launch_bounds__(256) void k_gather_active(Problem P, Work w, int unpack_t,
+                                                       int unpack_n) {
+  const RoundState* st = w.st;
+  const int nA = st->nA, n_unc = st->n_unc;
+  const int lane = threadIdx.x & 63;
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  const int W32 = 2 * w.w64;
+  const int kpad = 64 * w.w64;
+  const int knpad = 64 * P.wn;
+  const uint32_t* Ns32 = reinterpret_cast<const uint32_t*>(w.Ns);
+  for (int a = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); a < nA; a += waves) {
+    const int g = w.act[a];
+    const uint64_t* row = w.Ts + (size_t)g * P.wt;
+    for (int k0 = 0; k0 < kpad; k0 += 64) {
+      int k = k0 + lane;
+      int bit = 0;
+      if (k < n_unc) {
+        int s = w.cols[k];
+        bit = (int)((row[s >> 6] >> (s & 63)) & 1ull);
+      }
+      unsigned long long word = __ballot(bit);
+      if (lane < 2) w.TA[(size_t)a * W32 + (k0 >> 5) + lane] = (uint32_t)(word >> (32 * lane));
+      if (unpack_t) w.A8[(size_t)a * kpad + k] = (int8_t)bit;
+    }
+    if (lane < kMaxWN32)
+      w.NA[(size_t)a * kMaxWN32 + lane] = lane < 2 * P.wn ? Ns32[(size_t)g * 2 * P.wn + lane] : 0u;
+    if (unpack_n) {
+      const uint64_t* nrow = w.Ns + (size_t)g * P.wn;
+      for (int k0 = 0; k0 < knpad; k0 += 64) {
+        int k = k0 + lane;
+        w.N8[(size_t)a * knpad + k] = (int8_t)((nrow[k >> 6] >> (k & 63)) & 1ull);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- h = 1
+// Every active gene is a leaf: S = p*|T_g & U| + q*(N_n - |N_g|).
+__global__ __launch_bounds__(256) void k_h1(Problem P, Work w) {
+  const RoundState* st = w.st;
+  const int nA = st->nA;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int W32 = 2 * w.w64;
+  int bs = -1, btp = 0, bfp = 0, bi = 0;
+  for (int a = gw * 64 + lane; a < nA; a += kWavesPerGrid * 64) {
+    int tp = 0, fp = 0;
+    for (int k = 0; k < W32; ++k) tp += __popc(w.TA[(size_t)a * W32 + k]);
+    for (int k = 0; k < kMaxWN32; ++k) fp += __popc(w.NA[(size_t)a * kMaxWN32 + k]);
+    int s = P.p * tp + P.q * (P.n_normal - fp);
+    if (tp > 0 && (s > bs || (s == bs && a < bi))) { bs = s; btp = tp; bfp = fp; bi = a; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    int os = __shfl_xor(bs, o, 64), otp = __shfl_xor(btp, o, 64);
+    int ofp = __shfl_xor(bfp, o, 64), oi = __shfl_xor(bi, o, 64);
+    if (os > bs || (os == bs && os >= 0 && oi < bi)) { bs = os; btp = otp; bfp = ofp; bi = oi; }
+  }
+  if (lane == 0) {
+    Slot sl;
+    sl.s = bs; sl.tp = btp; sl.fp = bfp;
+    sl.idx[0] = bi; sl.idx[1] = sl.idx[2] = sl.idx[3] = 0; sl.pad = 0;
+    w.slots[gw] = sl;
+  }
+  if (gw == 0 && lane == 0) {
+    w.st->cnt.nonempty[1] = (unsigned long long)nA;
+    w.st->cnt.visited[1] = (unsigned long long)P.G;
+  }
+}
+
+__global__ void k_clear_slots(Slot* slots, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Slot e;
+  e.s = -1; e.tp = e.fp = 0; e.idx[0] = e.idx[1] = e.idx[2] = e.idx[3] = 0; e.pad = 0;
+  slots[i] = e;
+}
+
+// ------------------------------------------------------------- finish
+// One block: argmax over the slots of the phases used this round, the round
+// record, and the cover update U <- U & ~(U & T_g1 & ... & T_gh).
+__global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int phase_mask) {
+  __shared__ Slot red[16];
+  __shared__ int s_found;
+  __shared__ int32_t s_sidx[4];
+  RoundState* st = w.st;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int h = P.h;
+  Slot b;
+  b.s = -1; b.tp = b.fp = 0; b.idx[0] = b.idx[1] = b.idx[2] = b.idx[3] = 0; b.pad = 0;
+  for (int ph = 0; ph < kSlotPhases; ++ph) {
+    if (!((phase_mask >> ph) & 1)) continue;
+    for (int i = tid; i < kSlotsPerPhase; i += 1024) {
+      Slot c = w.slots[(size_t)ph * kSlotsPerPhase + i];
+      if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less4(c.idx, b.idx, h))) b = c;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    Slot c;
+    c.s = __shfl_xor(b.s, o, 64);
+    c.tp = __shfl_xor(b.tp, o, 64);
+    c.fp = __shfl_xor(b.fp, o, 64);
+    for (int i = 0; i < 4; ++i) c.idx[i] = __shfl_xor(b.idx[i], o, 64);
+    if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less4(c.idx, b.idx, h))) b = c;
+  }
+  if (lane == 0) red[wid] = b;
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 1; i < 16; ++i) {
+      Slot c = red[i];
+      if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less4(c.idx, b.idx, h))) b = c;
+    }
+    RoundRecord r;
+    r.h = h;
+    r.found = b.s >= 0;
+    if (r.found) {
+      // a slot index outside the active list would mean a corrupt slot
+      const int nA = st->nA;
+      for (int i = 0; i < h; ++i)
+        if (b.idx[i] < 0 || b.idx[i] >= nA || (i > 0 && b.idx[i] <= b.idx[i - 1])) r.found = 0;
+      if (b.tp <= 0) r.found = 0;
+      if (!r.found) st->overflow |= 2;
+    }
+    for (int i = 0; i < kMaxH; ++i) { r.sorted_idx[i] = -1; r.genes[i] = -1; }
+    r.tp = r.fp = r.tn = 0;
+    r.uncovered_before = st->n_unc;
+    r.score_num = 0;
+    r.score_den = (int64_t)P.q * (int64_t)(st->n_unc + P.n_normal);
+    if (r.found) {
+      for (int i = 0; i < h; ++i) {
+        int si = w.act[b.idx[i]];
+        r.sorted_idx[i] = si;
+        r.genes[i] = w.perm[si];
+        s_sidx[i] = si;
+      }
+      r.tp = b.tp;
+      r.fp = b.fp;
+      r.tn = P.n_normal - b.fp;
+      r.score_num = (int64_t)P.p * b.tp + (int64_t)P.q * r.tn;
+    }
+    *w.rec = r;
+    s_found = r.found;
+    st->found = r.found;
+  }
+  __syncthreads();
+  if (s_found && tid < P.wt) {
+    uint64_t cov = w.U[tid];
+    for (int i = 0; i < h; ++i) cov &= w.Ts[(size_t)s_sidx[i] * P.wt + tid];
+    w.U[tid] &= ~cov;
+  }
+  if (tid == 0) {
+    int cov = (P.n_tumor - st->n_unc) + (s_found ? b.tp : 0);
+    st->covered = cov;
+    st->rounds += s_found ? 1 : 0;
+    st->done = (!s_found) || cov >= w.target;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_gene_counts(const uint64_t* T, int64_t ts, const uint64_t* N, int64_t ns,
+                              int G, int wt, int wn, uint32_t* counts, hipStream_t s) {
+  // ids share the counts allocation's companion buffer: counts[G..2G) as int
+  int32_t* ids = reinterpret_cast<int32_t*>(counts + G);
+  k_gene_counts<<<(G + 255) / 256, 256, 0, s>>>(T, ts, N, ns, G, wt, wn, counts, ids);
+  return hipGetLastError();
+}
+
+hipError_t sort_genes(uint32_t* counts, uint32_t* counts_tmp, int32_t* ids, int32_t* perm, int G,
+                      void* tmp, size_t* tmp_bytes, hipStream_t s) {
+  return hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, counts, counts_tmp, ids, perm, G, 0,
+                                            32, s);
+}
+
+hipError_t launch_gather_sorted(const uint64_t* T, int64_t ts, const uint64_t* N, int64_t ns,
+                                const int32_t* perm, int G, int wt, int wn, uint64_t* Ts,
+                                uint64_t* Ns, hipStream_t s) {
+  k_gather_sorted<<<(G + 255) / 256, 256, 0, s>>>(T, ts, N, ns, perm, G, wt, wn, Ts, Ns);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_pad(const uint64_t* T, int64_t ts, int G, int n, int* bad,
+                            hipStream_t s) {
+  k_check_pad<<<(G + 255) / 256, 256, 0, s>>>(T, ts, G, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u(uint64_t* U, int wt, int n, hipStream_t s) {
+  k_fill_u<<<(wt + 63) / 64, 64, 0, s>>>(U, wt, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_begin(const Problem& P, const Work& w, hipStream_t s) {
+  k_round_begin<<<1, 64, 0, s>>>(P, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_active(const Problem& P, const Work& w, hipStream_t s) {
+  k_active_flags<<<(P.G + 255) / 256, 256, 0, s>>>(P, w);
+  k_active_scan<<<1, 1024, 0, s>>>(P, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_active(const Problem& P, const Work& w, bool unpack_tumor,
+                                bool unpack_normal, hipStream_t s) {
+  int blocks = (P.G + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  k_gather_active<<<blocks, 256, 0, s>>>(P, w, unpack_tumor ? 1 : 0, unpack_normal ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_h1(const Problem& P, const Work& w, hipStream_t s) {
+  k_h1<<<kPersistBlocks, kBlock, 0, s>>>(P, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, hipStream_t s) {
+  k_finish_round<<<1, 1024, 0, s>>>(P, w, phase_mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_slots(Slot* slots, int n, hipStream_t s) {
+  k_clear_slots<<<(n + 255) / 256, 256, 0, s>>>(slots, n);
+  return hipGetLastError();
+}
+
+}  // namespace pdfs

@@ -1,0 +1,151 @@
+// Internal declarations shared by the HIP kernels and the host orchestration
+// of libpdfs.  Not part of the public ABI (that is include/pdfs.h).
+//
+// Device data layout of one cohort (all in HBM, library-owned):
+//   Ts   uint64 [G][wt]   tumour rows in sorted (sparsest-first) order
+//   Ns   uint64 [G][wn]   normal rows in sorted order (wn >= 1, zero-padded)
+//   perm int32  [G]       sorted position -> caller gene id
+//   U    uint64 [wt]      uncovered tumour samples of the current round
+// Per-round workspace (DelCols done physically: only uncovered columns kept):
+//   cols int32  [n_tumor]       uncovered sample ids, ascending
+//   act  int32  [G]             active genes (sorted idx with T_g & U != 0)
+//   TA   uint32 [G][w32]        active tumour rows over uncovered columns
+//                               (w32 = 2*w64 words, zero padded)
+//   NA   uint32 [G][16]         active normal rows (all normals, zero padded)
+//   A8   int8   [G32][kpad]     active tumour rows unpacked to 0/1 bytes for
+//                               the int8 MFMA pair table (kpad = 64*w64)
+//   N8   int8   [G32][knpad]    same for normals (h = 2 only)
+//   pairs uint64 [cap]          non-empty pairs (a | b<<16 | count<<32)
+//   items  Item [cap]           DFS work items (pair batch x candidate range)
+//   slots  Slot [nslot]         per-wave best candidates for the argmax
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdfs {
+
+constexpr int kMaxH = 8;
+constexpr int kWave = 64;
+constexpr int kMaxW64 = 20;        // tumour words per row the DFS kernels take
+constexpr int kMaxWN32 = 16;       // normal 32-bit words per row (n_normal <= 512)
+constexpr int kPairBatch = 64;     // pairs per DFS batch (one per lane)
+constexpr int kPersistBlocks = 2048;
+constexpr int kBlock = 256;        // 4 waves per block
+constexpr int kWavesPerGrid = kPersistBlocks * (kBlock / kWave);
+constexpr int kSlotsPerPhase = kWavesPerGrid;
+constexpr int kSlotPhases = 3;     // pair kernel / seed DFS / main DFS
+
+enum PruneMode { kPruneNone = 0, kPruneEmpty = 1, kPruneBound = 2 };
+
+// Per-depth counters, index = depth.
+struct Counters {
+  unsigned long long visited[kMaxH + 1];
+  unsigned long long nonempty[kMaxH + 1];
+  unsigned long long bound_pruned[kMaxH + 1];
+};
+
+// One round's device-side state.  Written by the round kernels, read back by
+// the host once per round.
+struct RoundState {
+  int32_t n_unc;        // |U| at round start
+  int32_t nA;           // active genes
+  int32_t amax[kMaxH + 1];  // depth l: active genes with sorted idx <= G-h+l-1
+  int32_t found;        // 1 if the round found a combination
+  int32_t done;         // stop flag after the update
+  int32_t covered;      // tumour samples covered after this round
+  int32_t rounds;       // rounds completed (device count)
+  unsigned long long n_pairs;      // pairs emitted
+  unsigned long long n_work_pairs; // pairs kept for the DFS
+  unsigned long long n_items;      // DFS work items
+  unsigned long long cursor;       // work-item cursor
+  unsigned long long incumbent;    // bound key: (S+1)<<32 | (~a & 0xffff)<<16 | (~b & 0xffff)
+  int32_t seed_n;                  // pairs in the seed batch
+  int32_t overflow;                // bit 0: a list hit its capacity; bit 1: corrupt slot
+  Counters cnt;                    // this round's counters
+};
+
+// Result of one round (host-visible copy).
+struct RoundRecord {
+  int32_t found;
+  int32_t h;
+  int32_t sorted_idx[kMaxH];
+  int32_t genes[kMaxH];
+  int32_t tp, fp, tn, uncovered_before;
+  int64_t score_num, score_den;
+};
+
+struct Slot {
+  int32_t s;        // score, -1 = empty
+  int32_t tp, fp;
+  int32_t idx[4];   // active-list indices, ascending
+  int32_t pad;
+};
+
+struct Item {
+  uint32_t batch;   // pair batch (kPairBatch consecutive work pairs)
+  uint32_t c_lo;    // first depth-3 candidate (active index)
+  uint32_t c_hi;    // one past the last
+  uint32_t pad;
+};
+
+// Static problem description passed by value to kernels.
+struct Problem {
+  int32_t G, n_tumor, n_normal, wt, wn;
+  int32_t h;
+  int32_t p, q;
+  int32_t mode;
+};
+
+// Round workspace pointers.
+struct Work {
+  const uint64_t* Ts;
+  const uint64_t* Ns;
+  const int32_t* perm;
+  uint64_t* U;
+  int32_t* cols;
+  int32_t* act;
+  uint8_t* flags;
+  uint32_t* TA;
+  uint32_t* NA;
+  int8_t* A8;
+  int8_t* N8;
+  unsigned long long* pairs;
+  unsigned long long* work_pairs;
+  Item* items;
+  Slot* slots;
+  RoundState* st;
+  RoundRecord* rec;
+  unsigned long long pair_cap;
+  unsigned long long item_cap;
+  int32_t w64;       // compacted tumour words per row used this round
+  int32_t wn32;      // normal 32-bit words per row
+  int32_t target;    // covered-count stop target
+};
+
+// ---------------------------------------------------------------- launchers
+// create time
+hipError_t launch_gene_counts(const uint64_t* T, int64_t ts, const uint64_t* N, int64_t ns,
+                              int G, int wt, int wn, uint32_t* counts, hipStream_t s);
+hipError_t sort_genes(uint32_t* counts, uint32_t* counts_tmp, int32_t* ids, int32_t* perm, int G,
+                      void* tmp, size_t* tmp_bytes, hipStream_t s);
+hipError_t launch_gather_sorted(const uint64_t* T, int64_t ts, const uint64_t* N, int64_t ns,
+                                const int32_t* perm, int G, int wt, int wn, uint64_t* Ts,
+                                uint64_t* Ns, hipStream_t s);
+hipError_t launch_check_pad(const uint64_t* T, int64_t ts, int G, int n, int* bad, hipStream_t s);
+
+// per round
+hipError_t launch_round_begin(const Problem& P, const Work& w, hipStream_t s);
+hipError_t launch_active(const Problem& P, const Work& w, hipStream_t s);
+hipError_t launch_gather_active(const Problem& P, const Work& w, bool unpack_tumor,
+                                bool unpack_normal, hipStream_t s);
+hipError_t launch_h1(const Problem& P, const Work& w, hipStream_t s);
+hipError_t launch_pairs(const Problem& P, const Work& w, hipStream_t s);
+hipError_t launch_seed_select(const Problem& P, const Work& w, hipStream_t s);
+hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStream_t s);
+hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s);
+hipError_t launch_dfs(const Problem& P, const Work& w, int phase, hipStream_t s);
+hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, hipStream_t s);
+hipError_t launch_clear_slots(Slot* slots, int n, hipStream_t s);
+hipError_t launch_fill_u(uint64_t* U, int wt, int n, hipStream_t s);
+
+}  // namespace pdfs
