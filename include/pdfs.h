@@ -89,10 +89,16 @@ typedef struct {
     int64_t normal_stride_words;
 } pdfs_matrix;
 
+/* pdfs_options.flags */
+#define PDFS_OPT_TIME_KERNELS 1   /* time the pair-table and DFS launches with HIP
+                                     events on the context's stream (pdfs_stats) */
+
 typedef struct {
     int32_t prune_mode; /* PDFS_PRUNE_*                                  */
     int32_t device;     /* HIP device ordinal                            */
     void *stream;       /* hipStream_t on that device, or NULL           */
+    int32_t flags;      /* PDFS_OPT_* bits                               */
+    int32_t reserved;
 } pdfs_options;
 
 /* One chosen combination (one greedy round). */
@@ -123,6 +129,23 @@ typedef struct {
     int32_t rounds;
     int32_t reserved;
     int64_t ns_total;   /* host wall time of the call, nanoseconds */
+    /* Filled when the context was created with PDFS_OPT_TIME_KERNELS:
+     * index 0 = int8-MFMA pair-table kernel, 1 = depth-first kernel. */
+    int64_t kernel_ns[2];        /* summed HIP-event durations            */
+    int32_t kernel_launches[2];  /* launches timed                        */
+    /* Work the kernels had to do, counted inside them (always filled):
+     * pair_macs  = active pairs x |U| (one multiply-add per sample);
+     * dfs_visits[l] = depth-l (l = 3, 4) candidate intersections over active
+     *   genes; dfs_leaves = scored leaves; dfs_fp_leaves = leaves whose
+     *   normal intersection had to be counted; dfs_visit_words3/4 = depth-3/4
+     *   visits times ceil(|U|/64) of their round, summed (so words / visits
+     *   is the mean row length in 64-bit words). */
+    uint64_t pair_macs;
+    uint64_t dfs_visits[PDFS_MAX_H + 1];
+    uint64_t dfs_leaves;
+    uint64_t dfs_fp_leaves;
+    uint64_t dfs_visit_words3;   /* sum of visits x ceil(|U|/64), depth 3 */
+    uint64_t dfs_visit_words4;   /* same for depth 4 */
 } pdfs_stats;
 
 /* Copies the cohort to the device, sorts genes sparsest first and sets up the

@@ -20,8 +20,8 @@ MODES = {"none": 0, "empty": 1, "bound": 2}
 
 
 def build() -> str:
-    """Compile the oracle with gcc (plain C11, -O2)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+    """Compile the oracle with gcc (plain C11, -O2, hardware popcount)."""
+    cmd = ["gcc", "-O2", "-mpopcnt", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
            SRC, "-o", LIB + ".tmp"]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
@@ -55,6 +55,9 @@ def _declare(L):
     L.oracle_best.argtypes = [i32, i32, i32, i32, P, i32, P, P, i32, i64, i64, P, i32,
                               P, P, P, P]
     L.oracle_best.restype = ctypes.c_int
+    L.oracle_best_share.argtypes = [i32, i32, i32, i32, P, i32, P, P, i32, i64, i64, P, i32,
+                                    i32, i32, P, P, P, P]
+    L.oracle_best_share.restype = ctypes.c_int
     L.oracle_wsc.argtypes = [i32, i32, i32, i32, P, i32, P, i32, i64, i64, i32, i32, P,
                              i32, i32, P, P, P, P, P]
     L.oracle_wsc.restype = ctypes.c_int
@@ -115,6 +118,32 @@ def best(T, N, n_tumor, n_normal, h, p, q, U=None, mode="empty", perm=None, L=No
                           _ptr(cnt))
     if r < 0:
         raise ValueError("oracle_best: invalid arguments")
+    if r == 0:
+        return Best(False, (), (), 0, 0, 0, 0, counters_dict(cnt))
+    si = tuple(int(i) for i in idx[:h])
+    t, f = int(tp[0]), int(fp[0])
+    return Best(True, si, tuple(int(perm[i]) for i in si), t, f, n_normal - f,
+                p * t + q * (n_normal - f), counters_dict(cnt))
+
+
+def best_share(T, N, n_tumor, n_normal, h, p, q, g1_lo, g1_hi, U=None, mode="empty",
+               perm=None, L=None) -> Best:
+    """One round restricted to first genes in sorted positions [g1_lo, g1_hi)."""
+    T, N = _words(T), _words(N)
+    G, wt = T.shape
+    if perm is None:
+        perm = order(T, N, L)
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    U = full_mask(n_tumor, wt) if U is None else np.ascontiguousarray(U, dtype=np.uint64)
+    idx = np.zeros(MAX_H, dtype=np.int32)
+    tp = np.zeros(1, dtype=np.int64)
+    fp = np.zeros(1, dtype=np.int64)
+    cnt = np.zeros(3 * (MAX_H + 1), dtype=np.uint64)
+    r = (L or lib()).oracle_best_share(G, n_tumor, n_normal, wt, _ptr(T), N.shape[1], _ptr(N),
+                                       _ptr(perm), h, p, q, _ptr(U), MODES[mode], g1_lo, g1_hi,
+                                       _ptr(idx), _ptr(tp), _ptr(fp), _ptr(cnt))
+    if r < 0:
+        raise ValueError("oracle_best_share: invalid arguments")
     if r == 0:
         return Best(False, (), (), 0, 0, 0, 0, counters_dict(cnt))
     si = tuple(int(i) for i in idx[:h])

@@ -116,9 +116,11 @@ static void score_leaf(or_dfs *st, int64_t tp) {
     }
 }
 
-/* Fill depth l (1-based) with sorted indices lo..G-h+l-1. */
-static void descend(or_dfs *st, int l, int32_t lo) {
-    const int32_t hi = st->G - st->h + l - 1;
+/* Fill depth l (1-based) with sorted indices lo..G-h+l-1 (depth 1 may be
+ * cut to the share [lo, hi1)). */
+static void descend(or_dfs *st, int l, int32_t lo, int32_t hi1) {
+    int32_t hi = st->G - st->h + l - 1;
+    if (l == 1 && hi1 - 1 < hi) hi = hi1 - 1;
     const uint64_t *prev = st->y + (size_t)(l - 1) * st->wt;
     uint64_t *cur = st->y + (size_t)l * st->wt;
     for (int32_t i = lo; i <= hi; i++) {
@@ -138,7 +140,7 @@ static void descend(or_dfs *st, int l, int32_t lo) {
             st->bound_pruned[l]++;
             continue;
         }
-        descend(st, l + 1, i + 1);
+        descend(st, l + 1, i + 1, 0);
     }
 }
 
@@ -148,12 +150,43 @@ static void descend(or_dfs *st, int l, int32_t lo) {
  * exists, 0 otherwise, -1 on bad arguments.  counters: 3 x (OR_MAX_H+1)
  * uint64, added to (visited, nonempty, bound_pruned), index = depth.
  */
+static int best_share(int32_t G, int32_t n_tumor, int32_t n_normal, int32_t wt,
+                      const uint64_t *T, int32_t wn, const uint64_t *N,
+                      const int32_t *perm, int32_t h, int64_t p, int64_t q,
+                      const uint64_t *U, int32_t mode, int32_t g1_lo, int32_t g1_hi,
+                      int32_t *best_idx, int64_t *tp, int64_t *fp, uint64_t *counters);
+
 int oracle_best(int32_t G, int32_t n_tumor, int32_t n_normal, int32_t wt,
                 const uint64_t *T, int32_t wn, const uint64_t *N,
                 const int32_t *perm, int32_t h, int64_t p, int64_t q,
                 const uint64_t *U, int32_t mode, int32_t *best_idx,
                 int64_t *tp, int64_t *fp, uint64_t *counters) {
+    return best_share(G, n_tumor, n_normal, wt, T, wn, N, perm, h, p, q, U, mode, 0, G,
+                      best_idx, tp, fp, counters);
+}
+
+/*
+ * The same search restricted to first genes g1 in [g1_lo, g1_hi) (sorted
+ * positions): one rank's share when the outer loop is split into intervals
+ * (Sec. III-D).  Used to time a bounded sample of a round.
+ */
+int oracle_best_share(int32_t G, int32_t n_tumor, int32_t n_normal, int32_t wt,
+                      const uint64_t *T, int32_t wn, const uint64_t *N,
+                      const int32_t *perm, int32_t h, int64_t p, int64_t q,
+                      const uint64_t *U, int32_t mode, int32_t g1_lo, int32_t g1_hi,
+                      int32_t *best_idx, int64_t *tp, int64_t *fp, uint64_t *counters) {
+    return best_share(G, n_tumor, n_normal, wt, T, wn, N, perm, h, p, q, U, mode, g1_lo, g1_hi,
+                      best_idx, tp, fp, counters);
+}
+
+static int best_share(int32_t G, int32_t n_tumor, int32_t n_normal, int32_t wt,
+                      const uint64_t *T, int32_t wn, const uint64_t *N,
+                      const int32_t *perm, int32_t h, int64_t p, int64_t q,
+                      const uint64_t *U, int32_t mode, int32_t g1_lo, int32_t g1_hi,
+                      int32_t *best_idx, int64_t *tp, int64_t *fp, uint64_t *counters) {
     if (h < 1 || h > OR_MAX_H || h > G || q < 1 || p < 0 || n_tumor < 1) return -1;
+    if (g1_lo < 0) g1_lo = 0;
+    if (g1_hi > G) g1_hi = G;
     (void)n_tumor;
     or_dfs st;
     memset(&st, 0, sizeof(st));
@@ -162,7 +195,7 @@ int oracle_best(int32_t G, int32_t n_tumor, int32_t n_normal, int32_t wt,
     st.y = (uint64_t *)calloc((size_t)(h + 1) * wt, sizeof(uint64_t));
     st.z = (uint64_t *)calloc((size_t)(wn > 0 ? wn : 1), sizeof(uint64_t));
     memcpy(st.y, U, sizeof(uint64_t) * (size_t)wt);
-    descend(&st, 1, 0);
+    descend(&st, 1, g1_lo, g1_hi);
     if (counters) {
         for (int l = 0; l <= OR_MAX_H; l++) {
             counters[l] += st.visited[l];

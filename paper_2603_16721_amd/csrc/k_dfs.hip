@@ -146,7 +146,8 @@ struct Best {
 
 struct Tally {
   unsigned long long ne3, ne4, vis3, vis4, bp2, bp3;
-  __device__ void init() { ne3 = ne4 = vis3 = vis4 = bp2 = bp3 = 0; }
+  unsigned long long xv3, xv4, xfp;   // active-candidate visits, FP-counted leaves
+  __device__ void init() { ne3 = ne4 = vis3 = vis4 = bp2 = bp3 = xv3 = xv4 = xfp = 0; }
 };
 
 // Depth-4 pass over n <= 64 staged prefixes (queue entries lane | c << 6,
@@ -194,6 +195,7 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
     if (!__any(live)) return;
   }
   const bool zlive = live && znz != 0;
+  if (live) tl.xv4 += (unsigned long long)(nA - 1 - c);
   for (int d = c_first + 1; d < nA; ++d) {
     cu32* row = TA + (size_t)d * W;
     const int tp = popc_and<W>(y3, row);
@@ -203,7 +205,10 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
     tl.ne4 += __popcll(m);
     int fp = 0;
     if (__any(hit && zlive)) {
-      if (hit && zlive) fp = popc_and_n(z3, NA + (size_t)d * kMaxWN32);
+      if (hit && zlive) {
+        fp = popc_and_n(z3, NA + (size_t)d * kMaxWN32);
+        tl.xfp++;
+      }
     }
     if (hit) {
       const int sc = P.p * tp + P.q * (P.n_normal - fp);
@@ -279,6 +284,10 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
     uint32_t znz = 0;
 #pragma unroll
     for (int k = 0; k < kMaxWN32; ++k) znz |= z2[k];
+    if (valid) {
+      const int lo = c_lo > b + 1 ? c_lo : b + 1;
+      if (c_hi > lo) tl.xv3 += (unsigned long long)(c_hi - lo);
+    }
 
     int qn = 0;
     for (int c = c_lo; c < c_hi; ++c) {
@@ -291,7 +300,10 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
       if (H == 3) {
         int fp = 0;
         if (__any(hit && znz != 0)) {
-          if (hit && znz != 0) fp = popc_and_n(z2, NA + (size_t)c * kMaxWN32);
+          if (hit && znz != 0) {
+            fp = popc_and_n(z2, NA + (size_t)c * kMaxWN32);
+            tl.xfp++;
+          }
         }
         if (hit) {
           const int tp = popc_and<W>(y2, row);
@@ -341,6 +353,12 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
     }
   }
 
+  // per-lane work tallies -> wave sums
+  for (int o = 32; o > 0; o >>= 1) {
+    tl.xv3 += __shfl_xor(tl.xv3, o, 64);
+    tl.xv4 += __shfl_xor(tl.xv4, o, 64);
+    tl.xfp += __shfl_xor(tl.xfp, o, 64);
+  }
   // wave argmax -> slot
   for (int o = 32; o > 0; o >>= 1) {
     const int s2 = __shfl_xor(best.s, o, 64), tp2 = __shfl_xor(best.tp, o, 64);
@@ -361,6 +379,11 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
     if (tl.vis3) atomicAdd(&st->cnt.visited[3], tl.vis3);
     if (tl.bp2) atomicAdd(&st->cnt.bound_pruned[2], tl.bp2);
     if (tl.bp3) atomicAdd(&st->cnt.bound_pruned[3], tl.bp3);
+    if (tl.xv3) atomicAdd(&st->x_vis3, tl.xv3);
+    if (tl.xv4) atomicAdd(&st->x_vis4, tl.xv4);
+    if (tl.xfp) atomicAdd(&st->x_fp_leaves, tl.xfp);
+    const unsigned long long leaves = H == 3 ? tl.ne3 : tl.ne4;
+    if (leaves) atomicAdd(&st->x_leaves, leaves);
   }
 }
 

@@ -102,6 +102,7 @@ __global__ void k_round_begin(Problem P, Work w) {
     st->incumbent = 0;
     st->seed_n = 0;
     st->overflow = 0;
+    st->x_vis3 = st->x_vis4 = st->x_leaves = st->x_fp_leaves = 0;
   }
   for (int l = lane; l <= kMaxH; l += 64) {
     st->amax[l] = 0;

@@ -48,6 +48,11 @@ struct pdfs_ctx {
   RoundRecord* h_rec = nullptr;
   std::vector<int32_t> h_perm;
   std::string err;
+  bool time_kernels = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // per-call accumulation of the timed launches
+  int64_t kernel_ns[2] = {0, 0};
+  int32_t kernel_launches[2] = {0, 0};
 };
 
 namespace {
@@ -79,6 +84,8 @@ void release(pdfs_ctx* c) {
     if (p) (void)hipFree(p);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_rec) (void)hipHostFree(c->h_rec);
+  for (hipEvent_t e : c->ev)
+    if (e) (void)hipEventDestroy(e);
 }
 
 int words(int n) { return (n + 63) / 64; }
@@ -128,32 +135,77 @@ int32_t run_round(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int n_
   CK(c, launch_round_begin(P, w, s));
   CK(c, launch_active(P, w, s));
   CK(c, launch_gather_active(P, w, h >= 2, h == 2, s));
+  const bool tk = c->time_kernels;
   if (h == 1) {
     CK(c, launch_h1(P, w, s));
-  } else if (h == 2) {
-    CK(c, launch_pairs(P, w, s));
   } else {
+    if (tk) CK(c, hipEventRecord(c->ev[0], s));
     CK(c, launch_pairs(P, w, s));
-    CK(c, launch_make_items(P, w, false, s));
-    CK(c, launch_dfs(P, w, 2, s));
+    if (tk) CK(c, hipEventRecord(c->ev[1], s));
+    if (h >= 3) {
+      CK(c, launch_make_items(P, w, false, s));
+      if (tk) CK(c, hipEventRecord(c->ev[2], s));
+      CK(c, launch_dfs(P, w, 2, s));
+      if (tk) CK(c, hipEventRecord(c->ev[3], s));
+    }
   }
   // slot phases written this round: 0 = h<=2 kernels, 2 = main DFS
   CK(c, launch_finish_round(P, w, h <= 2 ? 1 : 4, s));
   CK(c, hipMemcpyAsync(c->h_st, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
   CK(c, hipMemcpyAsync(c->h_rec, c->rec, sizeof(RoundRecord), hipMemcpyDeviceToHost, s));
   CK(c, hipStreamSynchronize(s));
+  if (tk && h >= 2) {
+    float ms = 0.f;
+    CK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    c->kernel_ns[0] += (int64_t)(ms * 1e6);
+    c->kernel_launches[0] += 1;
+    if (h >= 3) {
+      CK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+      c->kernel_ns[1] += (int64_t)(ms * 1e6);
+      c->kernel_launches[1] += 1;
+    }
+  }
   if (c->h_st->overflow & 2) return fail(c, PDFS_ERR_DEVICE, "corrupt per-wave result slot");
   if (c->h_st->overflow)
     return fail(c, PDFS_ERR_OUT_OF_MEMORY, "pair or item list capacity exceeded");
   return PDFS_OK;
 }
 
-void add_counters(pdfs_stats* st, const RoundState& r) {
+void add_counters(pdfs_stats* st, const RoundState& r, int h) {
   if (!st) return;
   for (int l = 0; l <= PDFS_MAX_H; ++l) {
     st->visited[l] += r.cnt.visited[l];
     st->nonempty[l] += r.cnt.nonempty[l];
     st->bound_pruned[l] += r.cnt.bound_pruned[l];
+  }
+  const unsigned long long wu = (unsigned long long)words(r.n_unc);
+  if (h >= 2) {
+    // every active pair within the depth-1/2 loop bounds, times |U|
+    const unsigned long long a1 = (unsigned long long)r.amax[1];
+    const unsigned long long a2 = (unsigned long long)r.amax[2];
+    unsigned long long pairs = 0;
+    if (a1 > 0) pairs = a1 * a2 - a1 * (a1 + 1) / 2;   // sum over i < a1 of (a2 - 1 - i)
+    st->pair_macs += pairs * (unsigned long long)r.n_unc;
+  }
+  st->dfs_visits[3] += r.x_vis3;
+  st->dfs_visits[4] += r.x_vis4;
+  st->dfs_visit_words3 += r.x_vis3 * wu;
+  st->dfs_visit_words4 += r.x_vis4 * wu;
+  st->dfs_leaves += r.x_leaves;
+  st->dfs_fp_leaves += r.x_fp_leaves;
+}
+
+void begin_stats(pdfs_ctx* c, pdfs_stats* st) {
+  if (st) memset(st, 0, sizeof(*st));
+  c->kernel_ns[0] = c->kernel_ns[1] = 0;
+  c->kernel_launches[0] = c->kernel_launches[1] = 0;
+}
+
+void end_stats(pdfs_ctx* c, pdfs_stats* st) {
+  if (!st) return;
+  for (int i = 0; i < 2; ++i) {
+    st->kernel_ns[i] = c->kernel_ns[i];
+    st->kernel_launches[i] = c->kernel_launches[i];
   }
 }
 
@@ -253,6 +305,7 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   c->device = opt ? opt->device : 0;
   c->stream = opt ? static_cast<hipStream_t>(opt->stream) : nullptr;
   c->prune_mode = mode;
+  c->time_kernels = opt && (opt->flags & PDFS_OPT_TIME_KERNELS);
   c->G = m->G; c->n_tumor = m->n_tumor; c->n_normal = m->n_normal;
   c->wt = wt; c->wn = wn_in > 0 ? wn_in : 1;
   c->w64_max = pdfs::dfs_row_words(wt);
@@ -273,6 +326,8 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   CKC(hipSetDevice(c->device));
   hipStream_t s = c->stream;
   const int G = m->G;
+  if (c->time_kernels)
+    for (hipEvent_t& e : c->ev) CKC(hipEventCreate(&e));
 
   // Stage the caller's matrices on the device (strided as given).
   const uint64_t* dT = m->tumor;
@@ -391,7 +446,7 @@ int32_t pdfs_best_combo(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q, const ui
   if (rc != PDFS_OK) return rc;
   if (!out) return fail(c, PDFS_ERR_INVALID_ARG, "out is NULL");
   auto t0 = std::chrono::steady_clock::now();
-  if (stats) memset(stats, 0, sizeof(*stats));
+  begin_stats(c, stats);
   int n_unc = c->n_tumor;
   if (uncovered) {
     if (!mask_pad_ok(uncovered, c->n_tumor, c->wt))
@@ -406,8 +461,9 @@ int32_t pdfs_best_combo(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q, const ui
   if (n_unc == 0) return PDFS_NO_COMBO;
   rc = run_round(c, h, p, q, c->n_tumor + 1, n_unc);
   if (rc != PDFS_OK) return rc;
-  add_counters(stats, *c->h_st);
+  add_counters(stats, *c->h_st, h);
   if (stats) {
+    end_stats(c, stats);
     stats->rounds = c->h_rec->found ? 1 : 0;
     stats->ns_total = std::chrono::duration_cast<std::chrono::nanoseconds>(
                           std::chrono::steady_clock::now() - t0).count();
@@ -425,7 +481,7 @@ int32_t pdfs_wsc_run(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q, int32_t tar
   if (!n_out || cap < 0 || (cap > 0 && !out))
     return fail(c, PDFS_ERR_INVALID_ARG, "bad output arguments");
   auto t0 = std::chrono::steady_clock::now();
-  if (stats) memset(stats, 0, sizeof(*stats));
+  begin_stats(c, stats);
   *n_out = 0;
   const int K = target_covered > 0 ? target_covered : c->n_tumor;
   int n_unc = c->n_tumor;
@@ -442,7 +498,7 @@ int32_t pdfs_wsc_run(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q, int32_t tar
   while (c->n_tumor - n_unc < K && (max_rounds <= 0 || rounds < max_rounds) && n_unc > 0) {
     rc = run_round(c, h, p, q, K, n_unc);
     if (rc != PDFS_OK) return rc;
-    add_counters(stats, *c->h_st);
+    add_counters(stats, *c->h_st, h);
     const RoundRecord& r = *c->h_rec;
     if (!r.found) break;
     if (r.tp <= 0 || r.tp > n_unc) return fail(c, PDFS_ERR_DEVICE, "round made no progress");
@@ -457,6 +513,7 @@ int32_t pdfs_wsc_run(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q, int32_t tar
     CK(c, hipStreamSynchronize(c->stream));
   }
   if (stats) {
+    end_stats(c, stats);
     stats->rounds = rounds;
     stats->ns_total = std::chrono::duration_cast<std::chrono::nanoseconds>(
                           std::chrono::steady_clock::now() - t0).count();

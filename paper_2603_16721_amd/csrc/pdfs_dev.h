@@ -62,6 +62,8 @@ struct RoundState {
   int32_t seed_n;                  // pairs in the seed batch
   int32_t overflow;                // bit 0: a list hit its capacity; bit 1: corrupt slot
   Counters cnt;                    // this round's counters
+  // work the DFS kernels had to do (active candidates only)
+  unsigned long long x_vis3, x_vis4, x_leaves, x_fp_leaves;
 };
 
 // Result of one round (host-visible copy).

@@ -38,9 +38,13 @@ class pdfs_matrix(ctypes.Structure):
                 ("tumor_stride_words", ctypes.c_int64), ("normal_stride_words", ctypes.c_int64)]
 
 
+PDFS_OPT_TIME_KERNELS = 1
+
+
 class pdfs_options(ctypes.Structure):
     _fields_ = [("prune_mode", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class pdfs_combo(ctypes.Structure):
@@ -56,7 +60,11 @@ class pdfs_stats(ctypes.Structure):
                 ("nonempty", ctypes.c_uint64 * (MAX_H + 1)),
                 ("bound_pruned", ctypes.c_uint64 * (MAX_H + 1)),
                 ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("ns_total", ctypes.c_int64)]
+                ("ns_total", ctypes.c_int64),
+                ("kernel_ns", ctypes.c_int64 * 2), ("kernel_launches", ctypes.c_int32 * 2),
+                ("pair_macs", ctypes.c_uint64), ("dfs_visits", ctypes.c_uint64 * (MAX_H + 1)),
+                ("dfs_leaves", ctypes.c_uint64), ("dfs_fp_leaves", ctypes.c_uint64),
+                ("dfs_visit_words3", ctypes.c_uint64), ("dfs_visit_words4", ctypes.c_uint64)]
 
 
 EXPORTS = ["pdfs_create", "pdfs_destroy", "pdfs_set_prune_mode", "pdfs_best_combo",
@@ -131,11 +139,12 @@ def _matrix_arg(tumor, normal, n_tumor, n_normal):
     return m, keep
 
 
-def pdfs_create(tumor, normal, n_tumor, n_normal, prune_mode="bound", device=0, stream=None):
+def pdfs_create(tumor, normal, n_tumor, n_normal, prune_mode="bound", device=0, stream=None,
+                flags=0):
     """Returns an opaque context handle (int).  Raises PdfsError on failure."""
     m, keep = _matrix_arg(tumor, normal, n_tumor, n_normal)
     mode = PRUNE_MODES[prune_mode] if isinstance(prune_mode, str) else int(prune_mode)
-    opt = pdfs_options(prune_mode=mode, device=device, stream=stream)
+    opt = pdfs_options(prune_mode=mode, device=device, stream=stream, flags=flags)
     out = ctypes.c_void_p()
     rc = lib.pdfs_create(ctypes.byref(m), ctypes.byref(opt), ctypes.byref(out))
     del keep
@@ -159,7 +168,11 @@ def stats_dict(s: pdfs_stats, h: int):
     return {"visited": [int(v) for v in s.visited[:MAX_H + 1]],
             "nonempty": [int(v) for v in s.nonempty[:MAX_H + 1]],
             "bound_pruned": [int(v) for v in s.bound_pruned[:MAX_H + 1]],
-            "rounds": int(s.rounds), "ns_total": int(s.ns_total)}
+            "rounds": int(s.rounds), "ns_total": int(s.ns_total),
+            "kernel_ns": [int(v) for v in s.kernel_ns], "kernel_launches": [int(v) for v in s.kernel_launches],
+            "pair_macs": int(s.pair_macs), "dfs_visits": [int(v) for v in s.dfs_visits],
+            "dfs_leaves": int(s.dfs_leaves), "dfs_fp_leaves": int(s.dfs_fp_leaves),
+            "dfs_visit_words3": int(s.dfs_visit_words3), "dfs_visit_words4": int(s.dfs_visit_words4)}
 
 
 def combo_dict(c: pdfs_combo):
@@ -210,10 +223,12 @@ class Solver:
     """Owns one context for a cohort (packed uint64 rows, LSB-first samples)."""
 
     def __init__(self, tumor, normal, n_tumor, n_normal, prune_mode="bound", device=0,
-                 stream=None):
+                 stream=None, time_kernels=False):
         self.n_tumor = n_tumor
         self.n_normal = n_normal
-        self.ctx = pdfs_create(tumor, normal, n_tumor, n_normal, prune_mode, device, stream)
+        self.ctx = None
+        self.ctx = pdfs_create(tumor, normal, n_tumor, n_normal, prune_mode, device, stream,
+                               PDFS_OPT_TIME_KERNELS if time_kernels else 0)
 
     def close(self):
         if self.ctx:
