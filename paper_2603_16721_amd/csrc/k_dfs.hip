@@ -233,8 +233,12 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
   const int wib = threadIdx.x >> 6;
   const int gw = blockIdx.x * (kBlock / kWave) + wib;
   uint32_t* q = qbuf[wib];
-  const unsigned long long npairs = st->n_work_pairs;
+  // phase 1 expands the seed list, phase 2 the (filtered) work list
+  const unsigned long long* __restrict__ plist = phase == 1 ? w.seed_pairs : w.work_pairs;
+  const unsigned long long npairs =
+      phase == 1 ? (st->n_seed < kSeedCap ? st->n_seed : kSeedCap) : st->n_work_pairs;
   const uint32_t nitems = (uint32_t)uniform((int)st->n_items);
+  const int nA_all = uniform(st->nA);
   const __attribute__((address_space(4))) Item* items =
       (const __attribute__((address_space(4))) Item*)w.items;
   cu32* TA = (cu32*)w.TA;
@@ -257,10 +261,11 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
     const uint32_t first_chunk = (uint32_t)uniform((int)items[it].pad) & 1u;
     const unsigned long long pi = (unsigned long long)batch * kPairBatch + lane;
     bool valid = pi < npairs;
-    const unsigned long long e = valid ? w.work_pairs[pi] : 0ull;
+    const unsigned long long e = valid ? plist[pi] : 0ull;
     const int a = (int)(e & 0xffff);
     const int b = (int)((e >> 16) & 0xffff);
     const int ct = (int)((e >> 32) & 0xffff);
+    valid = valid && a < b && b < nA_all;   // list entries always satisfy this
     if (P.mode == kPruneBound) {
       inc = load_incumbent(st);
       const bool drop = valid && dominated(P.p * ct + P.q * P.n_normal, a, b, inc);
@@ -387,39 +392,56 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
   }
 }
 
-// One wave per batch of kPairBatch work pairs: the batch's depth-3 candidate
-// range (min b + 1 .. amax[3]) cut into chunks.
-__global__ __launch_bounds__(256) void k_make_items(Problem P, Work w) {
+// Work items: batches of kPairBatch consecutive list pairs, each batch's
+// depth-3 candidate range (min b + 1 .. amax[3]) cut into chunks.  One wave
+// handles 64 batches (lane j holds batch j's range) and reserves their items
+// with a single atomic.
+__global__ __launch_bounds__(256) void k_make_items(Problem P, Work w, int seed, int chunk0) {
   RoundState* st = w.st;
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const unsigned long long np = st->n_work_pairs;
+  const unsigned long long* __restrict__ list = seed ? w.seed_pairs : w.work_pairs;
+  const unsigned long long np =
+      seed ? (st->n_seed < kSeedCap ? st->n_seed : kSeedCap) : st->n_work_pairs;
   const unsigned long long nb = (np + kPairBatch - 1) / kPairBatch;
   const int amax3 = st->amax[3];
   // chunk length so that the item list cannot overflow
-  unsigned long long chunk = kChunk;
+  unsigned long long chunk = (unsigned long long)chunk0;
   const unsigned long long room = w.item_cap > nb ? w.item_cap - nb : 1;
   const unsigned long long need = (nb * (unsigned long long)st->nA + room - 1) / room;
   if (need > chunk) chunk = need;
-  for (unsigned long long bi = gw; bi < nb; bi += kWavesPerGrid) {
-    const unsigned long long pi = bi * kPairBatch + lane;
-    int b = 0x7fffffff;
-    if (pi < np) b = (int)((w.work_pairs[pi] >> 16) & 0xffff);
-    for (int o = 32; o > 0; o >>= 1) b = min(b, __shfl_xor(b, o, 64));
-    const int lo = b + 1, hi = amax3;
-    if (lo >= hi) continue;
-    const unsigned long long len = (unsigned long long)(hi - lo);
-    const unsigned long long n = (len + chunk - 1) / chunk;
+  for (unsigned long long blk = (unsigned long long)gw * 64; blk < nb;
+       blk += (unsigned long long)gridDim.x * (blockDim.x >> 6) * 64) {
+    int mylo = 0, mylen = 0;
+    const int nbat = (int)((nb - blk) < 64 ? (nb - blk) : 64);
+    for (int j = 0; j < nbat; ++j) {
+      const unsigned long long pi = (blk + j) * kPairBatch + lane;
+      int b = 0x7fffffff;
+      if (pi < np) b = (int)((list[pi] >> 16) & 0xffff);
+      for (int o = 32; o > 0; o >>= 1) b = min(b, __shfl_xor(b, o, 64));
+      if (lane == j) {
+        mylo = b + 1;
+        mylen = amax3 > mylo ? amax3 - mylo : 0;
+      }
+    }
+    const unsigned long long n = mylen > 0 ? ((unsigned long long)mylen + chunk - 1) / chunk : 0;
+    unsigned long long incl = n;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const unsigned long long total = __shfl(incl, 63, 64);
+    if (total == 0) continue;
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&st->n_items, n);
-    base = __shfl(base, 0, 64);
-    for (unsigned long long k = lane; k < n; k += 64) {
+    if (lane == 0) base = atomicAdd(&st->n_items, total);
+    base = __shfl(base, 0, 64) + incl - n;
+    for (unsigned long long k = 0; k < n; ++k) {
       if (base + k < w.item_cap) {
         Item it;
-        it.batch = (uint32_t)bi;
-        it.c_lo = (uint32_t)(lo + k * chunk);
-        unsigned long long e = lo + (k + 1) * chunk;
-        it.c_hi = (uint32_t)(e < (unsigned long long)hi ? e : hi);
+        it.batch = (uint32_t)(blk + lane);
+        it.c_lo = (uint32_t)(mylo + k * chunk);
+        const unsigned long long e = mylo + (k + 1) * chunk;
+        it.c_hi = (uint32_t)(e < (unsigned long long)amax3 ? e : (unsigned long long)amax3);
         it.pad = (k == 0) ? 1u : 0u;
         w.items[base + k] = it;
       }
@@ -433,11 +455,20 @@ __global__ void k_clamp_items(Work w) {
     st->n_items = w.item_cap;
     st->overflow = 1;
   }
-  if (st->n_pairs > w.pair_cap) {
-    st->n_pairs = w.pair_cap;
-    st->overflow = 1;
-  }
   st->cursor = 0;
+}
+
+__global__ void k_reset_items(Work w) {
+  w.st->n_items = 0;
+  w.st->cursor = 0;
+}
+
+// Bound mode: the pair list is final; the seed and work lists start empty.
+__global__ void k_begin_bound_lists(Work w) {
+  RoundState* st = w.st;
+  if (st->n_pairs > w.pair_cap) { st->n_pairs = w.pair_cap; st->overflow = 1; }
+  st->n_work_pairs = 0;
+  st->n_seed = 0;
 }
 
 __global__ void k_use_all_pairs(Work w) {
@@ -446,6 +477,91 @@ __global__ void k_use_all_pairs(Work w) {
   if (n > w.pair_cap) { n = w.pair_cap; st->overflow = 1; }
   st->n_pairs = n;
   st->n_work_pairs = n;
+}
+
+// ---- bound mode: seed selection and pair filtering -------------------------
+// Histogram of the pair counts (C_T) of all emitted pairs.
+__global__ __launch_bounds__(256) void k_pair_hist(Work w) {
+  __shared__ uint32_t h[kMaxCount + 1];
+  for (int v = threadIdx.x; v <= kMaxCount; v += blockDim.x) h[v] = 0u;
+  __syncthreads();
+  const unsigned long long np = w.st->n_pairs < w.pair_cap ? w.st->n_pairs : w.pair_cap;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < np;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const int ct = (int)((w.pairs[i] >> 32) & 0xffff);
+    atomicAdd(&h[ct < kMaxCount ? ct : kMaxCount], 1u);
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v <= kMaxCount; v += blockDim.x)
+    if (h[v]) atomicAdd(&w.hist[v], h[v]);
+}
+
+// Threshold t: the largest count such that at least kSeedPairs pairs reach it.
+__global__ void k_seed_threshold(Work w) {
+  if (threadIdx.x != 0) return;
+  unsigned long long cum = 0;
+  int t = 1;
+  for (int v = kMaxCount; v >= 1; --v) {
+    cum += w.hist[v];
+    if (cum >= (unsigned long long)kSeedPairs) { t = v; break; }
+  }
+  w.st->seed_t = t;
+}
+
+// Pairs with count >= t go to the seed list (up to kSeedCap) and are marked
+// (bit 63) in the full list so that the main phase skips them.
+__global__ __launch_bounds__(256) void k_seed_select(Work w) {
+  RoundState* st = w.st;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const unsigned long long np = st->n_pairs < w.pair_cap ? st->n_pairs : w.pair_cap;
+  const int t = st->seed_t;
+  for (unsigned long long i0 = (unsigned long long)gw * 64; i0 < np;
+       i0 += (unsigned long long)gridDim.x * (blockDim.x >> 6) * 64) {
+    const unsigned long long i = i0 + lane;
+    unsigned long long e = i < np ? w.pairs[i] : 0ull;
+    const bool sel = i < np && (int)((e >> 32) & 0xffff) >= t;
+    const unsigned long long m = __ballot(sel);
+    if (!m) continue;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&st->n_seed, (unsigned long long)__popcll(m));
+    base = __shfl(base, 0, 64);
+    const unsigned long long pos = base + __popcll(m & ((1ull << lane) - 1));
+    if (sel && pos < kSeedCap) {
+      w.seed_pairs[pos] = e;
+      w.pairs[i] = e | (1ull << 63);
+    }
+  }
+}
+
+// Main-phase list: every unmarked pair whose bound can still reach the
+// incumbent found by the seed phase.  Waves append their survivors in list
+// order, so batches keep the locality of the pair table's tiles.
+__global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
+  RoundState* st = w.st;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const unsigned long long np = st->n_pairs < w.pair_cap ? st->n_pairs : w.pair_cap;
+  const unsigned long long inc = load_incumbent(st);
+  unsigned long long dropped = 0;
+  for (unsigned long long i0 = (unsigned long long)gw * 64; i0 < np;
+       i0 += (unsigned long long)gridDim.x * (blockDim.x >> 6) * 64) {
+    const unsigned long long i = i0 + lane;
+    const unsigned long long e = i < np ? w.pairs[i] : (1ull << 63);
+    const int a = (int)(e & 0xffff), b = (int)((e >> 16) & 0xffff);
+    const int ct = (int)((e >> 32) & 0xffff);
+    const bool seeded = (e >> 63) != 0;
+    const bool drop = !seeded && dominated(P.p * ct + P.q * P.n_normal, a, b, inc);
+    const bool keep = !seeded && !drop;
+    dropped += __popcll(__ballot(drop));
+    const unsigned long long m = __ballot(keep);
+    if (!m) continue;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&st->n_work_pairs, (unsigned long long)__popcll(m));
+    base = __shfl(base, 0, 64);
+    if (keep) w.work_pairs[base + __popcll(m & ((1ull << lane) - 1))] = e;
+  }
+  if (lane == 0 && dropped) atomicAdd(&st->cnt.bound_pruned[2], dropped);
 }
 
 template <int H>
@@ -476,11 +592,29 @@ int dfs_row_words(int n) {
   return -1;
 }
 
-hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStream_t s) {
-  (void)seed;
+hipError_t launch_use_all_pairs(const Work& w, hipStream_t s) {
   k_use_all_pairs<<<1, 1, 0, s>>>(w);
-  k_make_items<<<kPersistBlocks, kBlock, 0, s>>>(P, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStream_t s) {
+  k_reset_items<<<1, 1, 0, s>>>(w);
+  k_make_items<<<kPersistBlocks / 8, kBlock, 0, s>>>(P, w, seed ? 1 : 0, seed ? 32 : kChunk);
   k_clamp_items<<<1, 1, 0, s>>>(w);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_select(const Problem& P, const Work& w, hipStream_t s) {
+  (void)P;
+  k_begin_bound_lists<<<1, 1, 0, s>>>(w);
+  k_pair_hist<<<256, 256, 0, s>>>(w);
+  k_seed_threshold<<<1, 64, 0, s>>>(w);
+  k_seed_select<<<kPersistBlocks / 4, kBlock, 0, s>>>(w);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s) {
+  k_filter_pairs<<<kPersistBlocks / 4, kBlock, 0, s>>>(P, w);
   return hipGetLastError();
 }
 

@@ -100,10 +100,12 @@ __global__ void k_round_begin(Problem P, Work w) {
     st->n_items = 0;
     st->cursor = 0;
     st->incumbent = 0;
-    st->seed_n = 0;
+    st->n_seed = 0;
+    st->seed_t = 0;
     st->overflow = 0;
     st->x_vis3 = st->x_vis4 = st->x_leaves = st->x_fp_leaves = 0;
   }
+  for (int v = lane; v <= kMaxCount; v += 64) w.hist[v] = 0u;
   for (int l = lane; l <= kMaxH; l += 64) {
     st->amax[l] = 0;
     st->cnt.visited[l] = 0;

@@ -38,6 +38,9 @@ struct pdfs_ctx {
   int8_t* A8 = nullptr;
   int8_t* N8 = nullptr;
   unsigned long long* pairs = nullptr;
+  unsigned long long* work_pairs = nullptr;   // bound mode only
+  unsigned long long* seed_pairs = nullptr;
+  uint32_t* hist = nullptr;
   unsigned long long pair_cap = 0;
   Item* items = nullptr;
   unsigned long long item_cap = 0;
@@ -79,7 +82,8 @@ hipError_t dalloc(T** p, size_t n) {
 
 void release(pdfs_ctx* c) {
   void* ptrs[] = {c->Ts, c->Ns, c->perm, c->U, c->cols, c->act, c->flags, c->TA, c->NA,
-                  c->A8, c->N8, c->pairs, c->items, c->slots, c->st, c->rec};
+                  c->A8, c->N8, c->pairs, c->work_pairs, c->seed_pairs, c->hist,
+                  c->items, c->slots, c->st, c->rec};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_st) (void)hipHostFree(c->h_st);
@@ -102,7 +106,10 @@ int32_t ensure_workspace(pdfs_ctx* c, int h) {
     if (ic < (1ull << 20)) ic = 1ull << 20;
     c->item_cap = ic;
     CK(c, dalloc(&c->items, (size_t)ic));
+    CK(c, dalloc(&c->seed_pairs, (size_t)kSeedCap));
   }
+  if (h >= 3 && c->prune_mode == PDFS_PRUNE_BOUND && !c->work_pairs)
+    CK(c, dalloc(&c->work_pairs, (size_t)c->pair_cap));
   if (h == 2 && !c->N8) {
     size_t rows = (size_t)((c->nA_max + 31) / 32 * 32 + 32);
     CK(c, dalloc(&c->N8, rows * 64 * (size_t)c->wn));
@@ -114,7 +121,9 @@ Work make_work(pdfs_ctx* c, int w64, int target) {
   Work w;
   w.Ts = c->Ts; w.Ns = c->Ns; w.perm = c->perm; w.U = c->U; w.cols = c->cols; w.act = c->act;
   w.flags = c->flags; w.TA = c->TA; w.NA = c->NA; w.A8 = c->A8; w.N8 = c->N8;
-  w.pairs = c->pairs; w.work_pairs = c->pairs; w.items = c->items; w.slots = c->slots;
+  w.pairs = c->pairs;
+  w.work_pairs = (c->prune_mode == PDFS_PRUNE_BOUND && c->work_pairs) ? c->work_pairs : c->pairs;
+  w.seed_pairs = c->seed_pairs; w.hist = c->hist; w.items = c->items; w.slots = c->slots;
   w.st = c->st; w.rec = c->rec; w.pair_cap = c->pair_cap; w.item_cap = c->item_cap;
   w.w64 = w64; w.wn32 = 2 * c->wn; w.target = target;
   return w;
@@ -143,14 +152,28 @@ int32_t run_round(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int n_
     CK(c, launch_pairs(P, w, s));
     if (tk) CK(c, hipEventRecord(c->ev[1], s));
     if (h >= 3) {
-      CK(c, launch_make_items(P, w, false, s));
-      if (tk) CK(c, hipEventRecord(c->ev[2], s));
+      if (c->prune_mode == PDFS_PRUNE_BOUND) {
+        // seed phase: expand the highest-count pairs first so that the
+        // incumbent is close to the round's answer, then keep only the pairs
+        // whose bound can still reach it
+        CK(c, launch_seed_select(P, w, s));
+        CK(c, launch_make_items(P, w, true, s));
+        if (tk) CK(c, hipEventRecord(c->ev[2], s));
+        CK(c, launch_dfs(P, w, 1, s));
+        CK(c, launch_filter_pairs(P, w, s));
+        CK(c, launch_make_items(P, w, false, s));
+      } else {
+        CK(c, launch_use_all_pairs(w, s));
+        CK(c, launch_make_items(P, w, false, s));
+        if (tk) CK(c, hipEventRecord(c->ev[2], s));
+      }
       CK(c, launch_dfs(P, w, 2, s));
       if (tk) CK(c, hipEventRecord(c->ev[3], s));
     }
   }
-  // slot phases written this round: 0 = h<=2 kernels, 2 = main DFS
-  CK(c, launch_finish_round(P, w, h <= 2 ? 1 : 4, s));
+  // slot phases written this round: 0 = h<=2 kernels, 1 = seed DFS, 2 = main DFS
+  const int phases = h <= 2 ? 1 : (c->prune_mode == PDFS_PRUNE_BOUND ? 6 : 4);
+  CK(c, launch_finish_round(P, w, phases, s));
   CK(c, hipMemcpyAsync(c->h_st, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
   CK(c, hipMemcpyAsync(c->h_rec, c->rec, sizeof(RoundRecord), hipMemcpyDeviceToHost, s));
   CK(c, hipStreamSynchronize(s));
@@ -406,6 +429,7 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   CKC(dalloc(&c->st, 1));
   CKC(dalloc(&c->rec, 1));
   CKC(dalloc(&c->slots, (size_t)kSlotPhases * kSlotsPerPhase));
+  CKC(dalloc(&c->hist, (size_t)kMaxCount + 1));
   CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_st), sizeof(RoundState), hipHostMallocDefault));
   CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_rec), sizeof(RoundRecord), hipHostMallocDefault));
   CKC(hipMemsetAsync(c->st, 0, sizeof(RoundState), s));

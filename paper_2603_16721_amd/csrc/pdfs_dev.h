@@ -34,6 +34,9 @@ constexpr int kBlock = 256;        // 4 waves per block
 constexpr int kWavesPerGrid = kPersistBlocks * (kBlock / kWave);
 constexpr int kSlotsPerPhase = kWavesPerGrid;
 constexpr int kSlotPhases = 3;     // pair kernel / seed DFS / main DFS
+constexpr int kSeedPairs = 256;    // bound mode: pairs expanded first to set the incumbent
+constexpr int kSeedCap = 1024;     // seed list capacity (ties at the threshold)
+constexpr int kMaxCount = 1280;    // largest tumour count of a pair (n_tumor limit)
 
 enum PruneMode { kPruneNone = 0, kPruneEmpty = 1, kPruneBound = 2 };
 
@@ -59,7 +62,8 @@ struct RoundState {
   unsigned long long n_items;      // DFS work items
   unsigned long long cursor;       // work-item cursor
   unsigned long long incumbent;    // bound key: (S+1)<<32 | (~a & 0xffff)<<16 | (~b & 0xffff)
-  int32_t seed_n;                  // pairs in the seed batch
+  unsigned long long n_seed;       // pairs selected for the seed phase
+  int32_t seed_t;                  // seed threshold on the pair count
   int32_t overflow;                // bit 0: a list hit its capacity; bit 1: corrupt slot
   Counters cnt;                    // this round's counters
   // work the DFS kernels had to do (active candidates only)
@@ -112,7 +116,9 @@ struct Work {
   int8_t* A8;
   int8_t* N8;
   unsigned long long* pairs;
-  unsigned long long* work_pairs;
+  unsigned long long* work_pairs;   // == pairs unless bound mode filters them
+  unsigned long long* seed_pairs;   // [kSeedCap]
+  uint32_t* hist;                   // [kMaxCount + 1] pair-count histogram
   Item* items;
   Slot* slots;
   RoundState* st;
@@ -145,6 +151,7 @@ hipError_t launch_pairs(const Problem& P, const Work& w, hipStream_t s);
 hipError_t launch_seed_select(const Problem& P, const Work& w, hipStream_t s);
 hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStream_t s);
 hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s);
+hipError_t launch_use_all_pairs(const Work& w, hipStream_t s);
 hipError_t launch_dfs(const Problem& P, const Work& w, int phase, hipStream_t s);
 hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, hipStream_t s);
 hipError_t launch_clear_slots(Slot* slots, int n, hipStream_t s);
