@@ -30,6 +30,7 @@
 // to it with first two indices lexicographically above the key's -- then
 // every tuple under it loses to a tuple already found.
 #include "pdfs_dev.h"
+#include "slot_reduce.h"
 
 namespace pdfs {
 
@@ -231,14 +232,15 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
   RoundState* st = w.st;
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
-  const int gw = blockIdx.x * (kBlock / kWave) + wib;
   uint32_t* q = qbuf[wib];
   // phase 1 expands the seed list, phase 2 the (filtered) work list
   const unsigned long long* __restrict__ plist = phase == 1 ? w.seed_pairs : w.work_pairs;
   const unsigned long long npairs =
       phase == 1 ? (st->n_seed < kSeedCap ? st->n_seed : kSeedCap) : st->n_work_pairs;
-  const uint32_t nitems = (uint32_t)uniform((int)st->n_items);
+  const unsigned long long nit = st->n_items;
+  const uint32_t nitems = (uint32_t)uniform((int)(nit < w.item_cap ? nit : w.item_cap));
   const int nA_all = uniform(st->nA);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && nit > w.item_cap) st->overflow |= 1;
   const __attribute__((address_space(4))) Item* items =
       (const __attribute__((address_space(4))) Item*)w.items;
   cu32* TA = (cu32*)w.TA;
@@ -250,9 +252,23 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
   tl.init();
   unsigned long long inc = 0;
 
+  // Scheduling: wave g takes item g first (no atomic at launch); further
+  // items come from a shared cursor that counts past the first kWavesPerGrid.
+  // A plain read first, so that once the items are gone waves leave without
+  // queueing on the cursor's atomic.
+  const uint32_t gw = blockIdx.x * (kBlock / kWave) + wib;
+  bool first = true;
   for (;;) {
-    uint32_t it = 0;
-    if (lane == 0) it = (uint32_t)atomicAdd(&st->cursor, 1ull);
+    uint32_t it = nitems;
+    if (first) {
+      it = gw;
+      first = false;
+    } else if (lane == 0) {
+      const unsigned long long cur =
+          __hip_atomic_load(&st->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cur + kWavesPerGrid < nitems)
+        it = (uint32_t)(kWavesPerGrid + atomicAdd(&st->cursor, 1ull));
+    }
     it = (uint32_t)uniform((int)it);
     if (it >= nitems) break;
     const int c_lo = uniform((int)items[it].c_lo);
@@ -358,38 +374,28 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
     }
   }
 
-  // per-lane work tallies -> wave sums
-  for (int o = 32; o > 0; o >>= 1) {
-    tl.xv3 += __shfl_xor(tl.xv3, o, 64);
-    tl.xv4 += __shfl_xor(tl.xv4, o, 64);
-    tl.xfp += __shfl_xor(tl.xfp, o, 64);
-  }
-  // wave argmax -> slot
-  for (int o = 32; o > 0; o >>= 1) {
-    const int s2 = __shfl_xor(best.s, o, 64), tp2 = __shfl_xor(best.tp, o, 64);
-    const int fp2 = __shfl_xor(best.fp, o, 64);
-    const int j0 = __shfl_xor(best.i0, o, 64), j1 = __shfl_xor(best.i1, o, 64);
-    const int j2 = __shfl_xor(best.i2, o, 64), j3 = __shfl_xor(best.i3, o, 64);
-    if (s2 >= 0) best.offer(s2, tp2, fp2, j0, j1, j2, j3);
-  }
-  if (lane == 0) {
-    Slot sl;
+  // block argmax -> slot
+  Slot sl = empty_slot();
+  if (best.s >= 0) {
     sl.s = best.s; sl.tp = best.tp; sl.fp = best.fp;
     sl.idx[0] = best.i0; sl.idx[1] = best.i1; sl.idx[2] = best.i2; sl.idx[3] = best.i3;
-    sl.pad = 0;
-    w.slots[(size_t)phase * kSlotsPerPhase + gw] = sl;
-    if (tl.ne3) atomicAdd(&st->cnt.nonempty[3], tl.ne3);
-    if (H == 4 && tl.ne4) atomicAdd(&st->cnt.nonempty[4], tl.ne4);
-    if (H == 4 && tl.vis4) atomicAdd(&st->cnt.visited[4], tl.vis4);
-    if (tl.vis3) atomicAdd(&st->cnt.visited[3], tl.vis3);
-    if (tl.bp2) atomicAdd(&st->cnt.bound_pruned[2], tl.bp2);
-    if (tl.bp3) atomicAdd(&st->cnt.bound_pruned[3], tl.bp3);
-    if (tl.xv3) atomicAdd(&st->x_vis3, tl.xv3);
-    if (tl.xv4) atomicAdd(&st->x_vis4, tl.xv4);
-    if (tl.xfp) atomicAdd(&st->x_fp_leaves, tl.xfp);
-    const unsigned long long leaves = H == 3 ? tl.ne3 : tl.ne4;
-    if (leaves) atomicAdd(&st->x_leaves, leaves);
   }
+  block_best_to(&w.slots[(size_t)phase * kSlotsPerPhase + blockIdx.x], sl);
+  // wave-uniform counts are held by lane 0 only, per-lane ones by every lane
+  unsigned long long v[kTallyN] = {0};
+  if (lane == 0) {
+    v[kTNe3] = tl.ne3;
+    v[kTNe4] = H == 4 ? tl.ne4 : 0;
+    v[kTVis4] = H == 4 ? tl.vis4 : 0;
+    v[kTBp2] = tl.bp2;
+    v[kTBp3] = tl.bp3;
+    v[kTLeaves] = H == 3 ? tl.ne3 : tl.ne4;
+  }
+  v[kTVis3] = tl.vis3;
+  v[kTXv3] = tl.xv3;
+  v[kTXv4] = tl.xv4;
+  v[kTXfp] = tl.xfp;
+  block_tally_to(w.tallies + ((size_t)phase * kPersistBlocks + blockIdx.x) * kTallyN, v);
 }
 
 // Work items: batches of kPairBatch consecutive list pairs, each batch's
@@ -449,34 +455,26 @@ __global__ __launch_bounds__(256) void k_make_items(Problem P, Work w, int seed,
   }
 }
 
-__global__ void k_clamp_items(Work w) {
-  RoundState* st = w.st;
-  if (st->n_items > w.item_cap) {
-    st->n_items = w.item_cap;
-    st->overflow = 1;
-  }
-  st->cursor = 0;
-}
-
-__global__ void k_reset_items(Work w) {
-  w.st->n_items = 0;
-  w.st->cursor = 0;
-}
-
-// Bound mode: the pair list is final; the seed and work lists start empty.
+// Bound mode: the pair list is final; the seed and work lists and the item
+// list start empty.
 __global__ void k_begin_bound_lists(Work w) {
   RoundState* st = w.st;
   if (st->n_pairs > w.pair_cap) { st->n_pairs = w.pair_cap; st->overflow = 1; }
   st->n_work_pairs = 0;
   st->n_seed = 0;
+  st->n_items = 0;
+  st->cursor = 0;
 }
 
+// Empty-only mode: every emitted pair is expanded.
 __global__ void k_use_all_pairs(Work w) {
   RoundState* st = w.st;
   unsigned long long n = st->n_pairs;
   if (n > w.pair_cap) { n = w.pair_cap; st->overflow = 1; }
   st->n_pairs = n;
   st->n_work_pairs = n;
+  st->n_items = 0;
+  st->cursor = 0;
 }
 
 // ---- bound mode: seed selection and pair filtering -------------------------
@@ -496,16 +494,38 @@ __global__ __launch_bounds__(256) void k_pair_hist(Work w) {
     if (h[v]) atomicAdd(&w.hist[v], h[v]);
 }
 
-// Threshold t: the largest count such that at least kSeedPairs pairs reach it.
-__global__ void k_seed_threshold(Work w) {
-  if (threadIdx.x != 0) return;
-  unsigned long long cum = 0;
-  int t = 1;
-  for (int v = kMaxCount; v >= 1; --v) {
-    cum += w.hist[v];
-    if (cum >= (unsigned long long)kSeedPairs) { t = v; break; }
+// Threshold t: the largest count such that at least kSeedPairs pairs reach
+// it (1 if fewer pairs exist).  Every block computes it from the histogram.
+__device__ int seed_threshold(const uint32_t* __restrict__ hist) {
+  constexpr int kPer = (kMaxCount + kBlock) / kBlock;   // bins per thread, from the top
+  __shared__ unsigned int part[kBlock];
+  __shared__ int t_sh;
+  const int tid = threadIdx.x;
+  unsigned int sum = 0;
+  for (int k = 0; k < kPer; ++k) {
+    const int v = kMaxCount - tid * kPer - k;
+    if (v >= 1) sum += hist[v];
   }
-  w.st->seed_t = t;
+  part[tid] = sum;
+  if (tid == 0) t_sh = 1;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long cum = 0;
+    for (int i = 0; i < kBlock; ++i) {
+      if (cum + part[i] >= (unsigned long long)kSeedPairs) {
+        for (int k = 0; k < kPer; ++k) {
+          const int v = kMaxCount - i * kPer - k;
+          if (v < 1) break;
+          cum += hist[v];
+          if (cum >= (unsigned long long)kSeedPairs) { t_sh = v; break; }
+        }
+        break;
+      }
+      cum += part[i];
+    }
+  }
+  __syncthreads();
+  return t_sh;
 }
 
 // Pairs with count >= t go to the seed list (up to kSeedCap) and are marked
@@ -515,7 +535,8 @@ __global__ __launch_bounds__(256) void k_seed_select(Work w) {
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const unsigned long long np = st->n_pairs < w.pair_cap ? st->n_pairs : w.pair_cap;
-  const int t = st->seed_t;
+  const int t = seed_threshold(w.hist);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->seed_t = t;
   for (unsigned long long i0 = (unsigned long long)gw * 64; i0 < np;
        i0 += (unsigned long long)gridDim.x * (blockDim.x >> 6) * 64) {
     const unsigned long long i = i0 + lane;
@@ -544,6 +565,11 @@ __global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
   const unsigned long long np = st->n_pairs < w.pair_cap ? st->n_pairs : w.pair_cap;
   const unsigned long long inc = load_incumbent(st);
   unsigned long long dropped = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the seed phase's items are consumed; the main phase builds new ones
+    st->n_items = 0;
+    st->cursor = 0;
+  }
   for (unsigned long long i0 = (unsigned long long)gw * 64; i0 < np;
        i0 += (unsigned long long)gridDim.x * (blockDim.x >> 6) * 64) {
     const unsigned long long i = i0 + lane;
@@ -553,7 +579,8 @@ __global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
     const bool seeded = (e >> 63) != 0;
     const bool drop = !seeded && dominated(P.p * ct + P.q * P.n_normal, a, b, inc);
     const bool keep = !seeded && !drop;
-    dropped += __popcll(__ballot(drop));
+    const unsigned long long dm = __ballot(drop);
+    if (lane == 0) dropped += __popcll(dm);
     const unsigned long long m = __ballot(keep);
     if (!m) continue;
     unsigned long long base = 0;
@@ -561,7 +588,13 @@ __global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
     base = __shfl(base, 0, 64);
     if (keep) w.work_pairs[base + __popcll(m & ((1ull << lane) - 1))] = e;
   }
-  if (lane == 0 && dropped) atomicAdd(&st->cnt.bound_pruned[2], dropped);
+  // one atomic per block
+  __shared__ unsigned long long bsum;
+  if (threadIdx.x == 0) bsum = 0;
+  __syncthreads();
+  if (lane == 0 && dropped) atomicAdd(&bsum, dropped);
+  __syncthreads();
+  if (threadIdx.x == 0 && bsum) atomicAdd(&st->cnt.bound_pruned[2], bsum);
 }
 
 template <int H>
@@ -598,9 +631,7 @@ hipError_t launch_use_all_pairs(const Work& w, hipStream_t s) {
 }
 
 hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStream_t s) {
-  k_reset_items<<<1, 1, 0, s>>>(w);
-  k_make_items<<<kPersistBlocks / 8, kBlock, 0, s>>>(P, w, seed ? 1 : 0, seed ? 32 : kChunk);
-  k_clamp_items<<<1, 1, 0, s>>>(w);
+  k_make_items<<<kPersistBlocks / 4, kBlock, 0, s>>>(P, w, seed ? 1 : 0, seed ? 32 : kChunk);
   return hipGetLastError();
 }
 
@@ -608,13 +639,12 @@ hipError_t launch_seed_select(const Problem& P, const Work& w, hipStream_t s) {
   (void)P;
   k_begin_bound_lists<<<1, 1, 0, s>>>(w);
   k_pair_hist<<<256, 256, 0, s>>>(w);
-  k_seed_threshold<<<1, 64, 0, s>>>(w);
-  k_seed_select<<<kPersistBlocks / 4, kBlock, 0, s>>>(w);
+  k_seed_select<<<kPersistBlocks / 2, kBlock, 0, s>>>(w);
   return hipGetLastError();
 }
 
 hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s) {
-  k_filter_pairs<<<kPersistBlocks / 4, kBlock, 0, s>>>(P, w);
+  k_filter_pairs<<<kPersistBlocks / 2, kBlock, 0, s>>>(P, w);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "pdfs_dev.h"
+#include "slot_reduce.h"
 
 namespace pdfs {
 
@@ -188,13 +189,13 @@ __global__ __launch_bounds__(256) void k_gather_active(Problem P, Work w, int un
   const int lane = threadIdx.x & 63;
   const int waves = gridDim.x * (blockDim.x >> 6);
   const int W32 = 2 * w.w64;
-  const int kpad = 64 * w.w64;
-  const int knpad = 64 * P.wn;
+  const int kpad = unpacked_row_bytes(w.w64);
+  const int knpad = unpacked_row_bytes(P.wn);
   const uint32_t* Ns32 = reinterpret_cast<const uint32_t*>(w.Ns);
   for (int a = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); a < nA; a += waves) {
     const int g = w.act[a];
     const uint64_t* row = w.Ts + (size_t)g * P.wt;
-    for (int k0 = 0; k0 < kpad; k0 += 64) {
+    for (int k0 = 0; k0 < 64 * w.w64; k0 += 64) {
       int k = k0 + lane;
       int bit = 0;
       if (k < n_unc) {
@@ -205,14 +206,15 @@ __global__ __launch_bounds__(256) void k_gather_active(Problem P, Work w, int un
       if (lane < 2) w.TA[(size_t)a * W32 + (k0 >> 5) + lane] = (uint32_t)(word >> (32 * lane));
       if (unpack_t) w.A8[(size_t)a * kpad + k] = (int8_t)bit;
     }
+    if (unpack_t)
+      for (int k = 64 * w.w64 + lane; k < kpad; k += 64) w.A8[(size_t)a * kpad + k] = 0;
     if (lane < kMaxWN32)
       w.NA[(size_t)a * kMaxWN32 + lane] = lane < 2 * P.wn ? Ns32[(size_t)g * 2 * P.wn + lane] : 0u;
     if (unpack_n) {
       const uint64_t* nrow = w.Ns + (size_t)g * P.wn;
-      for (int k0 = 0; k0 < knpad; k0 += 64) {
-        int k = k0 + lane;
-        w.N8[(size_t)a * knpad + k] = (int8_t)((nrow[k >> 6] >> (k & 63)) & 1ull);
-      }
+      for (int k = lane; k < knpad; k += 64)
+        w.N8[(size_t)a * knpad + k] =
+            k < 64 * P.wn ? (int8_t)((nrow[k >> 6] >> (k & 63)) & 1ull) : (int8_t)0;
     }
   }
 }
@@ -233,17 +235,9 @@ __global__ __launch_bounds__(256) void k_h1(Problem P, Work w) {
     int s = P.p * tp + P.q * (P.n_normal - fp);
     if (tp > 0 && (s > bs || (s == bs && a < bi))) { bs = s; btp = tp; bfp = fp; bi = a; }
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    int os = __shfl_xor(bs, o, 64), otp = __shfl_xor(btp, o, 64);
-    int ofp = __shfl_xor(bfp, o, 64), oi = __shfl_xor(bi, o, 64);
-    if (os > bs || (os == bs && os >= 0 && oi < bi)) { bs = os; btp = otp; bfp = ofp; bi = oi; }
-  }
-  if (lane == 0) {
-    Slot sl;
-    sl.s = bs; sl.tp = btp; sl.fp = bfp;
-    sl.idx[0] = bi; sl.idx[1] = sl.idx[2] = sl.idx[3] = 0; sl.pad = 0;
-    w.slots[gw] = sl;
-  }
+  Slot sl = empty_slot();
+  if (bs >= 0) { sl.s = bs; sl.tp = btp; sl.fp = bfp; sl.idx[0] = bi; }
+  block_best_to(&w.slots[blockIdx.x], sl);
   if (gw == 0 && lane == 0) {
     w.st->cnt.nonempty[1] = (unsigned long long)nA;
     w.st->cnt.visited[1] = (unsigned long long)P.G;
@@ -253,21 +247,57 @@ __global__ __launch_bounds__(256) void k_h1(Problem P, Work w) {
 __global__ void k_clear_slots(Slot* slots, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  Slot e;
-  e.s = -1; e.tp = e.fp = 0; e.idx[0] = e.idx[1] = e.idx[2] = e.idx[3] = 0; e.pad = 0;
-  slots[i] = e;
+  slots[i] = empty_slot();
 }
 
 // ------------------------------------------------------------- finish
 // One block: argmax over the slots of the phases used this round, the round
 // record, and the cover update U <- U & ~(U & T_g1 & ... & T_gh).
-__global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int phase_mask) {
+__global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int phase_mask,
+                                                      int tally_mask) {
   __shared__ Slot red[16];
   __shared__ int s_found;
   __shared__ int32_t s_sidx[4];
+  __shared__ unsigned long long tsum[16][kTallyN];
   RoundState* st = w.st;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int h = P.h;
+  {
+    // per-block counter rows of the kernels that ran this round
+    unsigned long long v[kTallyN] = {0};
+    for (int ph = 0; ph < kSlotPhases; ++ph) {
+      if (!((tally_mask >> ph) & 1)) continue;
+      for (int b = tid; b < kPersistBlocks; b += 1024) {
+        const unsigned long long* row = w.tallies + ((size_t)ph * kPersistBlocks + b) * kTallyN;
+        for (int f = 0; f < kTallyN; ++f) v[f] += row[f];
+      }
+    }
+    for (int f = 0; f < kTallyN; ++f) {
+      unsigned long long x = v[f];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) tsum[wid][f] = x;
+    }
+    __syncthreads();
+    if (tid < kTallyN) {
+      unsigned long long x = 0;
+      for (int i = 0; i < 16; ++i) x += tsum[i][tid];
+      switch (tid) {
+        case kTNe2: st->cnt.nonempty[2] += x; break;
+        case kTVis3: st->cnt.visited[3] += x; break;
+        case kTNe3: st->cnt.nonempty[3] += x; break;
+        case kTNe4: st->cnt.nonempty[4] += x; break;
+        case kTVis4: st->cnt.visited[4] += x; break;
+        case kTBp2: st->cnt.bound_pruned[2] += x; break;
+        case kTBp3: st->cnt.bound_pruned[3] += x; break;
+        case kTXv3: st->x_vis3 += x; break;
+        case kTXv4: st->x_vis4 += x; break;
+        case kTXfp: st->x_fp_leaves += x; break;
+        case kTLeaves: st->x_leaves += x; break;
+        default: break;
+      }
+    }
+    __syncthreads();
+  }
   Slot b;
   b.s = -1; b.tp = b.fp = 0; b.idx[0] = b.idx[1] = b.idx[2] = b.idx[3] = 0; b.pad = 0;
   for (int ph = 0; ph < kSlotPhases; ++ph) {
@@ -397,8 +427,9 @@ hipError_t launch_h1(const Problem& P, const Work& w, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, hipStream_t s) {
-  k_finish_round<<<1, 1024, 0, s>>>(P, w, phase_mask);
+hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, int tally_mask,
+                               hipStream_t s) {
+  k_finish_round<<<1, 1024, 0, s>>>(P, w, phase_mask, tally_mask);
   return hipGetLastError();
 }
 

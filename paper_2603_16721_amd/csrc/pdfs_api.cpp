@@ -45,6 +45,7 @@ struct pdfs_ctx {
   Item* items = nullptr;
   unsigned long long item_cap = 0;
   Slot* slots = nullptr;
+  unsigned long long* tallies = nullptr;
   RoundState* st = nullptr;
   RoundRecord* rec = nullptr;
   RoundState* h_st = nullptr;
@@ -83,7 +84,7 @@ hipError_t dalloc(T** p, size_t n) {
 void release(pdfs_ctx* c) {
   void* ptrs[] = {c->Ts, c->Ns, c->perm, c->U, c->cols, c->act, c->flags, c->TA, c->NA,
                   c->A8, c->N8, c->pairs, c->work_pairs, c->seed_pairs, c->hist,
-                  c->items, c->slots, c->st, c->rec};
+                  c->items, c->slots, c->tallies, c->st, c->rec};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_st) (void)hipHostFree(c->h_st);
@@ -111,8 +112,8 @@ int32_t ensure_workspace(pdfs_ctx* c, int h) {
   if (h >= 3 && c->prune_mode == PDFS_PRUNE_BOUND && !c->work_pairs)
     CK(c, dalloc(&c->work_pairs, (size_t)c->pair_cap));
   if (h == 2 && !c->N8) {
-    size_t rows = (size_t)((c->nA_max + 31) / 32 * 32 + 32);
-    CK(c, dalloc(&c->N8, rows * 64 * (size_t)c->wn));
+    size_t rows = (size_t)((c->nA_max + 127) / 128 * 128 + 128);
+    CK(c, dalloc(&c->N8, rows * (size_t)unpacked_row_bytes(c->wn)));
   }
   return PDFS_OK;
 }
@@ -124,6 +125,7 @@ Work make_work(pdfs_ctx* c, int w64, int target) {
   w.pairs = c->pairs;
   w.work_pairs = (c->prune_mode == PDFS_PRUNE_BOUND && c->work_pairs) ? c->work_pairs : c->pairs;
   w.seed_pairs = c->seed_pairs; w.hist = c->hist; w.items = c->items; w.slots = c->slots;
+  w.tallies = c->tallies;
   w.st = c->st; w.rec = c->rec; w.pair_cap = c->pair_cap; w.item_cap = c->item_cap;
   w.w64 = w64; w.wn32 = 2 * c->wn; w.target = target;
   return w;
@@ -173,7 +175,9 @@ int32_t run_round(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int n_
   }
   // slot phases written this round: 0 = h<=2 kernels, 1 = seed DFS, 2 = main DFS
   const int phases = h <= 2 ? 1 : (c->prune_mode == PDFS_PRUNE_BOUND ? 6 : 4);
-  CK(c, launch_finish_round(P, w, phases, s));
+  // counter rows: 0 = pair table (h >= 2), 1 = seed DFS, 2 = main DFS
+  const int tallies = h == 1 ? 0 : (h == 2 ? 1 : (c->prune_mode == PDFS_PRUNE_BOUND ? 7 : 5));
+  CK(c, launch_finish_round(P, w, phases, tallies, s));
   CK(c, hipMemcpyAsync(c->h_st, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
   CK(c, hipMemcpyAsync(c->h_rec, c->rec, sizeof(RoundRecord), hipMemcpyDeviceToHost, s));
   CK(c, hipStreamSynchronize(s));
@@ -430,6 +434,7 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   CKC(dalloc(&c->rec, 1));
   CKC(dalloc(&c->slots, (size_t)kSlotPhases * kSlotsPerPhase));
   CKC(dalloc(&c->hist, (size_t)kMaxCount + 1));
+  CKC(dalloc(&c->tallies, (size_t)kSlotPhases * kPersistBlocks * kTallyN));
   CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_st), sizeof(RoundState), hipHostMallocDefault));
   CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_rec), sizeof(RoundRecord), hipHostMallocDefault));
   CKC(hipMemsetAsync(c->st, 0, sizeof(RoundState), s));
@@ -446,10 +451,11 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
     CKC(hipStreamSynchronize(s));
     c->nA_max = c->h_st->nA;
   }
-  const size_t rows = (size_t)((c->nA_max + 31) / 32 * 32 + 32);
+  // row padding: whole 128-row MFMA block tiles
+  const size_t rows = (size_t)((c->nA_max + 127) / 128 * 128 + 128);
   CKC(dalloc(&c->TA, rows * 2 * (size_t)c->w64_max));
   CKC(dalloc(&c->NA, rows * (size_t)kMaxWN32));
-  CKC(dalloc(&c->A8, rows * 64 * (size_t)c->w64_max));
+  CKC(dalloc(&c->A8, rows * (size_t)unpacked_row_bytes(c->w64_max)));
   *out = c;
   return PDFS_OK;
 #undef CKC

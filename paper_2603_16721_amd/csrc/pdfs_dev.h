@@ -12,9 +12,9 @@
 //   TA   uint32 [G][w32]        active tumour rows over uncovered columns
 //                               (w32 = 2*w64 words, zero padded)
 //   NA   uint32 [G][16]         active normal rows (all normals, zero padded)
-//   A8   int8   [G32][kpad]     active tumour rows unpacked to 0/1 bytes for
-//                               the int8 MFMA pair table (kpad = 64*w64)
-//   N8   int8   [G32][knpad]    same for normals (h = 2 only)
+//   A8   int8   [G128][kpad]    active tumour rows unpacked to 0/1 bytes for
+//                               the int8 MFMA pair table (kpad = 128*ceil(w64/2))
+//   N8   int8   [G128][knpad]   same for normals (h = 2 only)
 //   pairs uint64 [cap]          non-empty pairs (a | b<<16 | count<<32)
 //   items  Item [cap]           DFS work items (pair batch x candidate range)
 //   slots  Slot [nslot]         per-wave best candidates for the argmax
@@ -29,16 +29,20 @@ constexpr int kWave = 64;
 constexpr int kMaxW64 = 20;        // tumour words per row the DFS kernels take
 constexpr int kMaxWN32 = 16;       // normal 32-bit words per row (n_normal <= 512)
 constexpr int kPairBatch = 64;     // pairs per DFS batch (one per lane)
-constexpr int kPersistBlocks = 2048;
+constexpr int kPersistBlocks = 1024;  // persistent grids: ~1.3 resident rounds of waves
 constexpr int kBlock = 256;        // 4 waves per block
 constexpr int kWavesPerGrid = kPersistBlocks * (kBlock / kWave);
-constexpr int kSlotsPerPhase = kWavesPerGrid;
+constexpr int kSlotsPerPhase = kPersistBlocks;   // one argmax slot per block
 constexpr int kSlotPhases = 3;     // pair kernel / seed DFS / main DFS
 constexpr int kSeedPairs = 256;    // bound mode: pairs expanded first to set the incumbent
 constexpr int kSeedCap = 1024;     // seed list capacity (ties at the threshold)
 constexpr int kMaxCount = 1280;    // largest tumour count of a pair (n_tumor limit)
 
 enum PruneMode { kPruneNone = 0, kPruneEmpty = 1, kPruneBound = 2 };
+
+// Bytes per unpacked (one byte per sample) row for the MFMA pair table: the
+// row's 64-bit words times 64, rounded up to the kernel's 128-byte K chunk.
+__host__ __device__ constexpr int unpacked_row_bytes(int w64) { return 128 * ((w64 + 1) / 2); }
 
 // Per-depth counters, index = depth.
 struct Counters {
@@ -68,6 +72,23 @@ struct RoundState {
   Counters cnt;                    // this round's counters
   // work the DFS kernels had to do (active candidates only)
   unsigned long long x_vis3, x_vis4, x_leaves, x_fp_leaves;
+};
+
+// Per-block counter rows (summed by the round's finish kernel instead of
+// thousands of same-address atomics).  Row layout:
+enum TallyField {
+  kTNe2 = 0,      // nonempty[2]
+  kTVis3,         // visited[3]
+  kTNe3,          // nonempty[3]
+  kTNe4,          // nonempty[4]
+  kTVis4,         // visited[4]
+  kTBp2,          // bound_pruned[2]
+  kTBp3,          // bound_pruned[3]
+  kTXv3,          // active-candidate depth-3 visits
+  kTXv4,          // active-candidate depth-4 visits
+  kTXfp,          // leaves whose normal intersection was counted
+  kTLeaves,       // scored leaves
+  kTallyN = 16
 };
 
 // Result of one round (host-visible copy).
@@ -121,6 +142,7 @@ struct Work {
   uint32_t* hist;                   // [kMaxCount + 1] pair-count histogram
   Item* items;
   Slot* slots;
+  unsigned long long* tallies;      // [kSlotPhases][kPersistBlocks][kTallyN]
   RoundState* st;
   RoundRecord* rec;
   unsigned long long pair_cap;
@@ -153,7 +175,8 @@ hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStre
 hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s);
 hipError_t launch_use_all_pairs(const Work& w, hipStream_t s);
 hipError_t launch_dfs(const Problem& P, const Work& w, int phase, hipStream_t s);
-hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, hipStream_t s);
+hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, int tally_mask,
+                               hipStream_t s);
 hipError_t launch_clear_slots(Slot* slots, int n, hipStream_t s);
 hipError_t launch_fill_u(uint64_t* U, int wt, int n, hipStream_t s);
 

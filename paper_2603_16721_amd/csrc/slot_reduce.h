@@ -1,0 +1,69 @@
+// Exact (S desc, tuple asc) argmax of per-lane candidates: wave shuffles,
+// then one slot per block.  Device code only.
+#pragma once
+#include "pdfs_dev.h"
+
+namespace pdfs {
+
+__device__ __forceinline__ bool slot_better(const Slot& c, const Slot& b) {
+  if (c.s != b.s) return c.s > b.s;
+  if (c.s < 0) return false;
+  for (int i = 0; i < 4; ++i)
+    if (c.idx[i] != b.idx[i]) return c.idx[i] < b.idx[i];
+  return false;
+}
+
+__device__ __forceinline__ Slot empty_slot() {
+  Slot e;
+  e.s = -1; e.tp = e.fp = 0; e.idx[0] = e.idx[1] = e.idx[2] = e.idx[3] = 0; e.pad = 0;
+  return e;
+}
+
+__device__ __forceinline__ Slot wave_best(Slot b) {
+  for (int o = 32; o > 0; o >>= 1) {
+    Slot c;
+    c.s = __shfl_xor(b.s, o, 64);
+    c.tp = __shfl_xor(b.tp, o, 64);
+    c.fp = __shfl_xor(b.fp, o, 64);
+    for (int i = 0; i < 4; ++i) c.idx[i] = __shfl_xor(b.idx[i], o, 64);
+    c.pad = 0;
+    if (slot_better(c, b)) b = c;
+  }
+  return b;
+}
+
+// Every thread of the block calls this once; thread 0 writes the block's best.
+__device__ __forceinline__ void block_best_to(Slot* dst, Slot b) {
+  __shared__ Slot red[kBlock / kWave];
+  b = wave_best(b);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Slot r = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+      if (slot_better(red[i], r)) r = red[i];
+    *dst = r;
+  }
+}
+
+// Sums per-lane counters over the block; thread 0 writes the block's row.
+// vals: kTallyN values per thread (lanes may hold partial counts).
+__device__ __forceinline__ void block_tally_to(unsigned long long* row,
+                                               unsigned long long (&vals)[kTallyN]) {
+  __shared__ unsigned long long red[kBlock / kWave][kTallyN];
+  for (int f = 0; f < kTallyN; ++f) {
+    unsigned long long v = vals[f];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    vals[f] = v;
+  }
+  if ((threadIdx.x & 63) == 0)
+    for (int f = 0; f < kTallyN; ++f) red[threadIdx.x >> 6][f] = vals[f];
+  __syncthreads();
+  if (threadIdx.x < kTallyN) {
+    unsigned long long v = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) v += red[i][threadIdx.x];
+    row[threadIdx.x] = v;
+  }
+}
+
+}  // namespace pdfs
