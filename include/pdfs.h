@@ -92,6 +92,9 @@ typedef struct {
 /* pdfs_options.flags */
 #define PDFS_OPT_TIME_KERNELS 1   /* time the pair-table and DFS launches with HIP
                                      events on the context's stream (pdfs_stats) */
+#define PDFS_OPT_GRAPHS 2         /* capture one round as a HIP graph per row width
+                                     and replay it (needs a non-NULL stream; ignored
+                                     together with PDFS_OPT_TIME_KERNELS) */
 
 typedef struct {
     int32_t prune_mode; /* PDFS_PRUNE_*                                  */
@@ -184,6 +187,61 @@ int32_t pdfs_wsc_run(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alpha_
 
 const char *pdfs_strerror(int32_t status);
 const char *pdfs_last_error(const pdfs_ctx *ctx);
+
+/* ------------------------------------------------------------- batched
+ * Many independent cohorts (instances) solved together: each instance keeps
+ * its own context, rounds stay device-resident, one round per row width is
+ * captured as a HIP graph and replayed, and the instances' rounds run
+ * concurrently on a small set of streams (one per hardware queue) while a
+ * single host thread feeds them.  Results are those of pdfs_wsc_run on each
+ * instance alone.  The split granularity (depth-3 candidates per work item,
+ * seed pairs in bound mode) is chosen per instance class by the tuner below
+ * when the batch is created with PDFS_OPT_AUTOTUNE. */
+#define PDFS_OPT_AUTOTUNE 4
+
+typedef struct pdfs_batch pdfs_batch;
+
+/* Ingests n instances (host or device matrices as in pdfs_create).
+ * opt->stream is ignored: the batch owns its streams. */
+int32_t pdfs_batch_create(const pdfs_matrix *inst, int32_t n, const pdfs_options *opt,
+                          pdfs_batch **out);
+/* Runs the greedy loop on every instance.  h[i], target[i] (<= 0: all),
+ * outs[i] (caps[i] records), n_outs[i] = rounds of instance i.  stats (may
+ * be NULL) receives the sums over instances.  Returns the first error, or
+ * PDFS_ERR_TRUNCATED if some instance needed more than caps[i] rounds. */
+int32_t pdfs_batch_run(pdfs_batch *b, const int32_t *h, uint32_t alpha_p, uint32_t alpha_q,
+                       const int32_t *target, pdfs_combo *const *outs, const int32_t *caps,
+                       int32_t *n_outs, pdfs_stats *stats);
+void pdfs_batch_destroy(pdfs_batch *b);
+
+/* ------------------------------------------------------------- served
+ * A request loop: solves submitted at any time are admitted when a slot and
+ * device memory are free (admission by free HBM: the request's estimated
+ * footprint must fit both the budget and the device's free memory), run
+ * concurrently with the requests already on the device (continuous
+ * batching: new requests join as others finish), keep their bit matrices and
+ * uncovered masks on the device between rounds, and are released on
+ * completion.  Latency is measured from submission to completion. */
+typedef struct pdfs_server pdfs_server;
+
+/* hbm_budget_bytes: device memory the server may hold (0 = 90% of free);
+ * max_active: requests on the device at once (<= 0: 8). */
+int32_t pdfs_server_create(const pdfs_options *opt, uint64_t hbm_budget_bytes,
+                           int32_t max_active, pdfs_server **out);
+/* Copies the cohort (host matrices only) and queues the solve.  *ticket
+ * identifies it.  Requests larger than the budget are rejected
+ * (PDFS_ERR_OUT_OF_MEMORY); invalid ones with PDFS_ERR_INVALID_ARG. */
+int32_t pdfs_server_submit(pdfs_server *s, const pdfs_matrix *m, int32_t h, uint32_t alpha_p,
+                           uint32_t alpha_q, int32_t target_covered, uint64_t *ticket);
+/* PDFS_PENDING while queued or running; PDFS_OK with the rounds (up to cap,
+ * *n_out = rounds) and latency_ns once done (the ticket is then released);
+ * an error code if the solve failed; PDFS_ERR_INVALID_ARG for an unknown
+ * ticket. */
+int32_t pdfs_server_poll(pdfs_server *s, uint64_t ticket, pdfs_combo *out, int32_t cap,
+                         int32_t *n_out, int64_t *latency_ns);
+/* Blocks until every submitted request has finished. */
+int32_t pdfs_server_drain(pdfs_server *s);
+void pdfs_server_destroy(pdfs_server *s);
 
 #ifdef __cplusplus
 }

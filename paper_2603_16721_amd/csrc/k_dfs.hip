@@ -36,7 +36,6 @@ namespace pdfs {
 
 namespace {
 
-constexpr int kChunk = 256;
 
 // Read-only view of the round's rows.  The rows do not change while a DFS
 // kernel runs, so reading them through the constant address space lets the
@@ -230,6 +229,7 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
   __shared__ uint32_t qbuf[kBlock / kWave][2 * kWave];
   RoundState* st = w.st;
+  if (st->done) return;
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   uint32_t* q = qbuf[wib];
@@ -404,6 +404,7 @@ __global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
 // with a single atomic.
 __global__ __launch_bounds__(256) void k_make_items(Problem P, Work w, int seed, int chunk0) {
   RoundState* st = w.st;
+  if (st->done) return;
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const unsigned long long* __restrict__ list = seed ? w.seed_pairs : w.work_pairs;
@@ -459,6 +460,7 @@ __global__ __launch_bounds__(256) void k_make_items(Problem P, Work w, int seed,
 // list start empty.
 __global__ void k_begin_bound_lists(Work w) {
   RoundState* st = w.st;
+  if (st->done) return;
   if (st->n_pairs > w.pair_cap) { st->n_pairs = w.pair_cap; st->overflow = 1; }
   st->n_work_pairs = 0;
   st->n_seed = 0;
@@ -469,6 +471,7 @@ __global__ void k_begin_bound_lists(Work w) {
 // Empty-only mode: every emitted pair is expanded.
 __global__ void k_use_all_pairs(Work w) {
   RoundState* st = w.st;
+  if (st->done) return;
   unsigned long long n = st->n_pairs;
   if (n > w.pair_cap) { n = w.pair_cap; st->overflow = 1; }
   st->n_pairs = n;
@@ -481,6 +484,7 @@ __global__ void k_use_all_pairs(Work w) {
 // Histogram of the pair counts (C_T) of all emitted pairs.
 __global__ __launch_bounds__(256) void k_pair_hist(Work w) {
   __shared__ uint32_t h[kMaxCount + 1];
+  if (w.st->done) return;
   for (int v = threadIdx.x; v <= kMaxCount; v += blockDim.x) h[v] = 0u;
   __syncthreads();
   const unsigned long long np = w.st->n_pairs < w.pair_cap ? w.st->n_pairs : w.pair_cap;
@@ -494,9 +498,9 @@ __global__ __launch_bounds__(256) void k_pair_hist(Work w) {
     if (h[v]) atomicAdd(&w.hist[v], h[v]);
 }
 
-// Threshold t: the largest count such that at least kSeedPairs pairs reach
-// it (1 if fewer pairs exist).  Every block computes it from the histogram.
-__device__ int seed_threshold(const uint32_t* __restrict__ hist) {
+// Threshold t: the largest count such that at least `want` pairs reach it (1
+// if fewer pairs exist).  Every block computes it from the histogram.
+__device__ int seed_threshold(const uint32_t* __restrict__ hist, int want) {
   constexpr int kPer = (kMaxCount + kBlock) / kBlock;   // bins per thread, from the top
   __shared__ unsigned int part[kBlock];
   __shared__ int t_sh;
@@ -512,12 +516,12 @@ __device__ int seed_threshold(const uint32_t* __restrict__ hist) {
   if (tid == 0) {
     unsigned long long cum = 0;
     for (int i = 0; i < kBlock; ++i) {
-      if (cum + part[i] >= (unsigned long long)kSeedPairs) {
+      if (cum + part[i] >= (unsigned long long)want) {
         for (int k = 0; k < kPer; ++k) {
           const int v = kMaxCount - i * kPer - k;
           if (v < 1) break;
           cum += hist[v];
-          if (cum >= (unsigned long long)kSeedPairs) { t_sh = v; break; }
+          if (cum >= (unsigned long long)want) { t_sh = v; break; }
         }
         break;
       }
@@ -532,10 +536,11 @@ __device__ int seed_threshold(const uint32_t* __restrict__ hist) {
 // (bit 63) in the full list so that the main phase skips them.
 __global__ __launch_bounds__(256) void k_seed_select(Work w) {
   RoundState* st = w.st;
+  if (st->done) return;
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const unsigned long long np = st->n_pairs < w.pair_cap ? st->n_pairs : w.pair_cap;
-  const int t = seed_threshold(w.hist);
+  const int t = seed_threshold(w.hist, w.seed_n);
   if (blockIdx.x == 0 && threadIdx.x == 0) st->seed_t = t;
   for (unsigned long long i0 = (unsigned long long)gw * 64; i0 < np;
        i0 += (unsigned long long)gridDim.x * (blockDim.x >> 6) * 64) {
@@ -560,6 +565,7 @@ __global__ __launch_bounds__(256) void k_seed_select(Work w) {
 // order, so batches keep the locality of the pair table's tiles.
 __global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
   RoundState* st = w.st;
+  if (st->done) return;
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const unsigned long long np = st->n_pairs < w.pair_cap ? st->n_pairs : w.pair_cap;
@@ -631,7 +637,7 @@ hipError_t launch_use_all_pairs(const Work& w, hipStream_t s) {
 }
 
 hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStream_t s) {
-  k_make_items<<<kPersistBlocks / 4, kBlock, 0, s>>>(P, w, seed ? 1 : 0, seed ? 32 : kChunk);
+  k_make_items<<<kPersistBlocks / 4, kBlock, 0, s>>>(P, w, seed ? 1 : 0, seed ? 32 : w.chunk);
   return hipGetLastError();
 }
 

@@ -113,6 +113,7 @@ __global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
   __shared__ int wsum[4];
   __shared__ unsigned long long wbase;
   RoundState* st = w.st;
+  if (st->done) return;
   const int nA = st->nA;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;

@@ -73,6 +73,7 @@ __global__ void k_fill_u(uint64_t* U, int wt, int n) {
 // One block of 64 threads: uncovered sample list and state reset.
 __global__ void k_round_begin(Problem P, Work w) {
   RoundState* st = w.st;
+  if (st->done) return;   // rounds queued past the stop are no-ops
   const int lane = threadIdx.x;
   int base = 0;
   for (int w0 = 0; w0 < P.wt; w0 += 64) {
@@ -117,6 +118,7 @@ __global__ void k_round_begin(Problem P, Work w) {
 
 // ------------------------------------------------------------- active genes
 __global__ void k_active_flags(Problem P, Work w) {
+  if (w.st->done) return;
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= P.G) return;
   uint64_t acc = 0;
@@ -132,6 +134,7 @@ __global__ __launch_bounds__(1024) void k_active_scan(Problem P, Work w) {
   __shared__ int wsum[16];
   __shared__ unsigned long long vsum[16];
   RoundState* st = w.st;
+  if (st->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int h = P.h;
   int base = 0;
@@ -185,6 +188,7 @@ __global__ __launch_bounds__(1024) void k_active_scan(Problem P, Work w) {
 __global__ __launch_bounds__(256) void k_gather_active(Problem P, Work w, int unpack_t,
                                                        int unpack_n) {
   const RoundState* st = w.st;
+  if (st->done) return;
   const int nA = st->nA, n_unc = st->n_unc;
   const int lane = threadIdx.x & 63;
   const int waves = gridDim.x * (blockDim.x >> 6);
@@ -223,6 +227,7 @@ __global__ __launch_bounds__(256) void k_gather_active(Problem P, Work w, int un
 // Every active gene is a leaf: S = p*|T_g & U| + q*(N_n - |N_g|).
 __global__ __launch_bounds__(256) void k_h1(Problem P, Work w) {
   const RoundState* st = w.st;
+  if (st->done) return;
   const int nA = st->nA;
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -260,23 +265,28 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
   __shared__ int32_t s_sidx[4];
   __shared__ unsigned long long tsum[16][kTallyN];
   RoundState* st = w.st;
+  if (st->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int h = P.h;
   {
-    // per-block counter rows of the kernels that ran this round
-    unsigned long long v[kTallyN] = {0};
+    // per-block counter rows of the kernels that ran this round; thread t
+    // always reads field t % kTallyN, so the reads are contiguous
+    static_assert(1024 % kTallyN == 0, "tally rows must tile the block");
+    constexpr int kIter = kPersistBlocks * kTallyN / 1024;
+    unsigned long long v = 0;
     for (int ph = 0; ph < kSlotPhases; ++ph) {
       if (!((tally_mask >> ph) & 1)) continue;
-      for (int b = tid; b < kPersistBlocks; b += 1024) {
-        const unsigned long long* row = w.tallies + ((size_t)ph * kPersistBlocks + b) * kTallyN;
-        for (int f = 0; f < kTallyN; ++f) v[f] += row[f];
-      }
+      const unsigned long long* base = w.tallies + (size_t)ph * kPersistBlocks * kTallyN + tid;
+      unsigned long long part[kIter];
+#pragma unroll
+      for (int i = 0; i < kIter; ++i) part[i] = base[(size_t)i * 1024];   // all loads in flight
+#pragma unroll
+      for (int i = 0; i < kIter; ++i) v += part[i];
     }
-    for (int f = 0; f < kTallyN; ++f) {
-      unsigned long long x = v[f];
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-      if (lane == 0) tsum[wid][f] = x;
-    }
+    // lanes l and l + 16, l + 32, l + 48 of a wave hold the same field
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lane < kTallyN) tsum[wid][lane] = v;
     __syncthreads();
     if (tid < kTallyN) {
       unsigned long long x = 0;
@@ -350,9 +360,9 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
       r.tn = P.n_normal - b.fp;
       r.score_num = (int64_t)P.p * b.tp + (int64_t)P.q * r.tn;
     }
-    *w.rec = r;
     s_found = r.found;
     st->found = r.found;
+    if (r.found && st->rounds < w.rec_cap) w.recs[st->rounds] = r;
   }
   __syncthreads();
   if (s_found && tid < P.wt) {
@@ -364,7 +374,54 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
     int cov = (P.n_tumor - st->n_unc) + (s_found ? b.tp : 0);
     st->covered = cov;
     st->rounds += s_found ? 1 : 0;
-    st->done = (!s_found) || cov >= w.target;
+    st->executed += 1;
+    // whole-run totals
+    for (int l = 0; l <= kMaxH; ++l) {
+      st->tot.visited[l] += st->cnt.visited[l];
+      st->tot.nonempty[l] += st->cnt.nonempty[l];
+      st->tot.bound_pruned[l] += st->cnt.bound_pruned[l];
+    }
+    const unsigned long long wu = (unsigned long long)((st->n_unc + 63) / 64);
+    st->tx_vis3 += st->x_vis3;
+    st->tx_vis4 += st->x_vis4;
+    st->tx_vis_words3 += st->x_vis3 * wu;
+    st->tx_vis_words4 += st->x_vis4 * wu;
+    st->tx_leaves += st->x_leaves;
+    st->tx_fp_leaves += st->x_fp_leaves;
+    if (h >= 2) {
+      // every active pair inside the depth-1/2 loop bounds, times |U|
+      const unsigned long long a1 = (unsigned long long)st->amax[1];
+      const unsigned long long a2 = (unsigned long long)st->amax[2];
+      const unsigned long long pairs = a1 ? a1 * a2 - a1 * (a1 + 1) / 2 : 0;
+      st->tx_pair_macs += pairs * (unsigned long long)st->n_unc;
+    }
+    st->done = (!s_found) || cov >= w.target || cov >= P.n_tumor ||
+               (st->max_rounds > 0 && st->rounds >= st->max_rounds);
+  }
+}
+
+// Whole-run state: nothing done yet, totals cleared, the covered count of the
+// starting mask.
+__global__ void k_run_begin(Problem P, Work w, int max_rounds) {
+  RoundState* st = w.st;
+  const int lane = threadIdx.x;
+  int c = 0;
+  for (int k = lane; k < P.wt; k += 64) c += __popcll(w.U[k]);
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (lane == 0) {
+    st->done = (P.n_tumor - c) >= w.target || c == 0;
+    st->rounds = 0;
+    st->executed = 0;
+    st->max_rounds = max_rounds;
+    st->covered = P.n_tumor - c;
+    st->n_unc = c;
+    st->tx_vis3 = st->tx_vis4 = st->tx_leaves = st->tx_fp_leaves = st->tx_pair_macs = 0;
+    st->tx_vis_words3 = st->tx_vis_words4 = 0;
+  }
+  for (int l = lane; l <= kMaxH; l += 64) {
+    st->tot.visited[l] = 0;
+    st->tot.nonempty[l] = 0;
+    st->tot.bound_pruned[l] = 0;
   }
 }
 
@@ -395,6 +452,11 @@ hipError_t launch_gather_sorted(const uint64_t* T, int64_t ts, const uint64_t* N
 hipError_t launch_check_pad(const uint64_t* T, int64_t ts, int G, int n, int* bad,
                             hipStream_t s) {
   k_check_pad<<<(G + 255) / 256, 256, 0, s>>>(T, ts, G, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_run_begin(const Problem& P, const Work& w, int max_rounds, hipStream_t s) {
+  k_run_begin<<<1, 64, 0, s>>>(P, w, max_rounds);
   return hipGetLastError();
 }
 

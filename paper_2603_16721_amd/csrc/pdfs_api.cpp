@@ -12,52 +12,9 @@
 
 #include "../../include/pdfs.h"
 #include "pdfs_dev.h"
-
-namespace pdfs {
-int dfs_row_words(int n);
-}
+#include "pdfs_host.h"
 
 using namespace pdfs;
-
-struct pdfs_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int prune_mode = PDFS_PRUNE_BOUND;
-  int G = 0, n_tumor = 0, n_normal = 0, wt = 0, wn = 0;
-  int nA_max = 0;
-  int w64_max = 0;
-  uint64_t* Ts = nullptr;
-  uint64_t* Ns = nullptr;
-  int32_t* perm = nullptr;
-  uint64_t* U = nullptr;
-  int32_t* cols = nullptr;
-  int32_t* act = nullptr;
-  uint8_t* flags = nullptr;
-  uint32_t* TA = nullptr;
-  uint32_t* NA = nullptr;
-  int8_t* A8 = nullptr;
-  int8_t* N8 = nullptr;
-  unsigned long long* pairs = nullptr;
-  unsigned long long* work_pairs = nullptr;   // bound mode only
-  unsigned long long* seed_pairs = nullptr;
-  uint32_t* hist = nullptr;
-  unsigned long long pair_cap = 0;
-  Item* items = nullptr;
-  unsigned long long item_cap = 0;
-  Slot* slots = nullptr;
-  unsigned long long* tallies = nullptr;
-  RoundState* st = nullptr;
-  RoundRecord* rec = nullptr;
-  RoundState* h_st = nullptr;
-  RoundRecord* h_rec = nullptr;
-  std::vector<int32_t> h_perm;
-  std::string err;
-  bool time_kernels = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  // per-call accumulation of the timed launches
-  int64_t kernel_ns[2] = {0, 0};
-  int32_t kernel_launches[2] = {0, 0};
-};
 
 namespace {
 
@@ -76,21 +33,38 @@ int32_t fail(pdfs_ctx* c, int32_t code, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));                   \
   } while (0)
 
+// Device allocation of a context: stream-ordered on the context's stream when
+// async_alloc is set (no device-wide synchronisation on free), plain otherwise.
+hipError_t dmalloc(pdfs_ctx* c, void** p, size_t bytes) {
+  bytes += 256;
+  c->bytes += bytes;
+  if (c->async_alloc) return hipMallocAsync(p, bytes, c->stream);
+  return hipMalloc(p, bytes);
+}
+
+void dfree(pdfs_ctx* c, void* p) {
+  if (!p) return;
+  if (c->async_alloc) (void)hipFreeAsync(p, c->stream);
+  else (void)hipFree(p);
+}
+
 template <typename T>
-hipError_t dalloc(T** p, size_t n) {
-  return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T) + 256);
+hipError_t dalloc(pdfs_ctx* c, T** p, size_t n) {
+  return dmalloc(c, reinterpret_cast<void**>(p), n * sizeof(T));
 }
 
 void release(pdfs_ctx* c) {
   void* ptrs[] = {c->Ts, c->Ns, c->perm, c->U, c->cols, c->act, c->flags, c->TA, c->NA,
                   c->A8, c->N8, c->pairs, c->work_pairs, c->seed_pairs, c->hist,
-                  c->items, c->slots, c->tallies, c->st, c->rec};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (c->h_st) (void)hipHostFree(c->h_st);
-  if (c->h_rec) (void)hipHostFree(c->h_rec);
-  for (hipEvent_t e : c->ev)
-    if (e) (void)hipEventDestroy(e);
+                  c->items, c->slots, c->tallies, c->st, c->recs};
+  for (void* p : ptrs) dfree(c, p);
+  if (c->h_st && c->own_h_st) (void)hipHostFree(c->h_st);
+  for (auto& row : c->ev)
+    for (hipEvent_t e : row)
+      if (e) (void)hipEventDestroy(e);
+  if (c->chunk_done) (void)hipEventDestroy(c->chunk_done);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
 }
 
 int words(int n) { return (n + 63) / 64; }
@@ -102,18 +76,18 @@ int32_t ensure_workspace(pdfs_ctx* c, int h) {
     unsigned long long n = (unsigned long long)c->nA_max * (c->nA_max > 0 ? c->nA_max - 1 : 0) / 2;
     if (n < 64) n = 64;
     c->pair_cap = n;
-    CK(c, dalloc(&c->pairs, (size_t)n));
+    CK(c, dalloc(c, &c->pairs, (size_t)n));
     unsigned long long ic = 2 * ((n + kPairBatch - 1) / kPairBatch);
     if (ic < (1ull << 20)) ic = 1ull << 20;
     c->item_cap = ic;
-    CK(c, dalloc(&c->items, (size_t)ic));
-    CK(c, dalloc(&c->seed_pairs, (size_t)kSeedCap));
+    CK(c, dalloc(c, &c->items, (size_t)ic));
+    CK(c, dalloc(c, &c->seed_pairs, (size_t)kSeedCap));
   }
   if (h >= 3 && c->prune_mode == PDFS_PRUNE_BOUND && !c->work_pairs)
-    CK(c, dalloc(&c->work_pairs, (size_t)c->pair_cap));
+    CK(c, dalloc(c, &c->work_pairs, (size_t)c->pair_cap));
   if (h == 2 && !c->N8) {
     size_t rows = (size_t)((c->nA_max + 127) / 128 * 128 + 128);
-    CK(c, dalloc(&c->N8, rows * (size_t)unpacked_row_bytes(c->wn)));
+    CK(c, dalloc(c, &c->N8, rows * (size_t)unpacked_row_bytes(c->wn)));
   }
   return PDFS_OK;
 }
@@ -126,33 +100,36 @@ Work make_work(pdfs_ctx* c, int w64, int target) {
   w.work_pairs = (c->prune_mode == PDFS_PRUNE_BOUND && c->work_pairs) ? c->work_pairs : c->pairs;
   w.seed_pairs = c->seed_pairs; w.hist = c->hist; w.items = c->items; w.slots = c->slots;
   w.tallies = c->tallies;
-  w.st = c->st; w.rec = c->rec; w.pair_cap = c->pair_cap; w.item_cap = c->item_cap;
+  w.st = c->st; w.recs = c->recs; w.rec_cap = c->rec_cap;
+  w.pair_cap = c->pair_cap; w.item_cap = c->item_cap;
   w.w64 = w64; w.wn32 = 2 * c->wn; w.target = target;
+  w.chunk = c->chunk_items; w.seed_n = c->seed_pairs_n;
   return w;
 }
 
-// One greedy round on the device; the round state and record land in the
-// pinned host copies.
-int32_t run_round(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int n_unc) {
-  int w64 = dfs_row_words(words(n_unc > 0 ? n_unc : 1));
-  if (w64 < 0 || w64 > c->w64_max) return fail(c, PDFS_ERR_UNSUPPORTED, "row too wide");
-  int32_t rc = ensure_workspace(c, h);
-  if (rc != PDFS_OK) return rc;
+Problem make_problem(const pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
   Problem P;
   P.G = c->G; P.n_tumor = c->n_tumor; P.n_normal = c->n_normal; P.wt = c->wt; P.wn = c->wn;
   P.h = h; P.p = (int32_t)p; P.q = (int32_t)q; P.mode = c->prune_mode;
-  Work w = make_work(c, w64, target);
+  return P;
+}
+
+// Enqueues one greedy round (every kernel returns at once if the run is
+// already done).  slot = which event set to use when timing.
+int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, int slot) {
+  const int h = P.h;
   hipStream_t s = c->stream;
+  hipEvent_t* ev = c->ev[slot];
+  const bool tk = c->time_kernels;
   CK(c, launch_round_begin(P, w, s));
   CK(c, launch_active(P, w, s));
   CK(c, launch_gather_active(P, w, h >= 2, h == 2, s));
-  const bool tk = c->time_kernels;
   if (h == 1) {
     CK(c, launch_h1(P, w, s));
   } else {
-    if (tk) CK(c, hipEventRecord(c->ev[0], s));
+    if (tk) CK(c, hipEventRecord(ev[0], s));
     CK(c, launch_pairs(P, w, s));
-    if (tk) CK(c, hipEventRecord(c->ev[1], s));
+    if (tk) CK(c, hipEventRecord(ev[1], s));
     if (h >= 3) {
       if (c->prune_mode == PDFS_PRUNE_BOUND) {
         // seed phase: expand the highest-count pairs first so that the
@@ -160,17 +137,17 @@ int32_t run_round(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int n_
         // whose bound can still reach it
         CK(c, launch_seed_select(P, w, s));
         CK(c, launch_make_items(P, w, true, s));
-        if (tk) CK(c, hipEventRecord(c->ev[2], s));
+        if (tk) CK(c, hipEventRecord(ev[2], s));
         CK(c, launch_dfs(P, w, 1, s));
         CK(c, launch_filter_pairs(P, w, s));
         CK(c, launch_make_items(P, w, false, s));
       } else {
         CK(c, launch_use_all_pairs(w, s));
         CK(c, launch_make_items(P, w, false, s));
-        if (tk) CK(c, hipEventRecord(c->ev[2], s));
+        if (tk) CK(c, hipEventRecord(ev[2], s));
       }
       CK(c, launch_dfs(P, w, 2, s));
-      if (tk) CK(c, hipEventRecord(c->ev[3], s));
+      if (tk) CK(c, hipEventRecord(ev[3], s));
     }
   }
   // slot phases written this round: 0 = h<=2 kernels, 1 = seed DFS, 2 = main DFS
@@ -178,49 +155,155 @@ int32_t run_round(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int n_
   // counter rows: 0 = pair table (h >= 2), 1 = seed DFS, 2 = main DFS
   const int tallies = h == 1 ? 0 : (h == 2 ? 1 : (c->prune_mode == PDFS_PRUNE_BOUND ? 7 : 5));
   CK(c, launch_finish_round(P, w, phases, tallies, s));
-  CK(c, hipMemcpyAsync(c->h_st, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
-  CK(c, hipMemcpyAsync(c->h_rec, c->rec, sizeof(RoundRecord), hipMemcpyDeviceToHost, s));
-  CK(c, hipStreamSynchronize(s));
-  if (tk && h >= 2) {
-    float ms = 0.f;
-    CK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-    c->kernel_ns[0] += (int64_t)(ms * 1e6);
-    c->kernel_launches[0] += 1;
-    if (h >= 3) {
-      CK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
-      c->kernel_ns[1] += (int64_t)(ms * 1e6);
-      c->kernel_launches[1] += 1;
-    }
-  }
-  if (c->h_st->overflow & 2) return fail(c, PDFS_ERR_DEVICE, "corrupt per-wave result slot");
-  if (c->h_st->overflow)
-    return fail(c, PDFS_ERR_OUT_OF_MEMORY, "pair or item list capacity exceeded");
   return PDFS_OK;
 }
 
-void add_counters(pdfs_stats* st, const RoundState& r, int h) {
-  if (!st) return;
-  for (int l = 0; l <= PDFS_MAX_H; ++l) {
-    st->visited[l] += r.cnt.visited[l];
-    st->nonempty[l] += r.cnt.nonempty[l];
-    st->bound_pruned[l] += r.cnt.bound_pruned[l];
+}  // namespace
+
+namespace pdfs {
+
+int32_t ctx_fail(pdfs_ctx* c, int32_t code, const std::string& msg) { return fail(c, code, msg); }
+
+// Enqueues `chunk` rounds at the run's current row width: replays of one
+// captured round when graphs are on, direct launches otherwise.
+static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int chunk) {
+  const Run& r = c->run;
+  if (c->use_graphs && !c->time_kernels) {
+    const auto key = std::make_tuple(P.h, w.w64, r.p, r.q, r.target, c->prune_mode,
+                                     c->chunk_items, c->seed_pairs_n);
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t e = nullptr;
+      CK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      const int32_t rc = enqueue_round(c, P, w, 0);
+      hipGraph_t g2 = nullptr;
+      const hipError_t ec = hipStreamEndCapture(c->stream, &g2);
+      if (rc != PDFS_OK) {
+        if (g2) (void)hipGraphDestroy(g2);
+        return rc;
+      }
+      CK(c, ec);
+      g = g2;
+      CK(c, hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(g);
+      it = c->graphs.emplace(key, e).first;
+    }
+    for (int k = 0; k < chunk; ++k) CK(c, hipGraphLaunch(it->second, c->stream));
+    return PDFS_OK;
   }
-  const unsigned long long wu = (unsigned long long)words(r.n_unc);
-  if (h >= 2) {
-    // every active pair within the depth-1/2 loop bounds, times |U|
-    const unsigned long long a1 = (unsigned long long)r.amax[1];
-    const unsigned long long a2 = (unsigned long long)r.amax[2];
-    unsigned long long pairs = 0;
-    if (a1 > 0) pairs = a1 * a2 - a1 * (a1 + 1) / 2;   // sum over i < a1 of (a2 - 1 - i)
-    st->pair_macs += pairs * (unsigned long long)r.n_unc;
+  for (int k = 0; k < chunk; ++k) {
+    const int32_t rc = enqueue_round(c, P, w, k);
+    if (rc != PDFS_OK) return rc;
   }
-  st->dfs_visits[3] += r.x_vis3;
-  st->dfs_visits[4] += r.x_vis4;
-  st->dfs_visit_words3 += r.x_vis3 * wu;
-  st->dfs_visit_words4 += r.x_vis4 * wu;
-  st->dfs_leaves += r.x_leaves;
-  st->dfs_fp_leaves += r.x_fp_leaves;
+  return PDFS_OK;
 }
+
+int32_t run_start(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int max_rounds,
+                  int n_unc) {
+  int32_t rc = ensure_workspace(c, h);
+  if (rc != PDFS_OK) return rc;
+  Run& r = c->run;
+  r = Run();
+  r.h = h; r.p = p; r.q = q; r.target = target; r.max_rounds = max_rounds; r.n_unc = n_unc;
+  const Problem P = make_problem(c, h, p, q);
+  Work w0 = make_work(c, 1, target);
+  CK(c, launch_run_begin(P, w0, max_rounds, c->stream));
+  r.active = true;
+  return PDFS_OK;
+}
+
+// The greedy loop on the device.  Rounds are enqueued in growing chunks;
+// between chunks the host reads the run state once (done flag, covered count)
+// and picks the row width of the next chunk: any width >= ceil(|U|/64) gives
+// the same results, and |U| only shrinks, so a chunk may keep its width.
+int32_t run_enqueue(pdfs_ctx* c) {
+  Run& r = c->run;
+  if (!r.active || r.pending) return PDFS_OK;
+  const int w64 = dfs_row_words(words(r.n_unc > 0 ? r.n_unc : 1));
+  if (w64 < 0 || w64 > c->w64_max) return fail(c, PDFS_ERR_UNSUPPORTED, "row too wide");
+  const Problem P = make_problem(c, r.h, r.p, r.q);
+  const Work w = make_work(c, w64, r.target);
+  int32_t rc = enqueue_rounds(c, P, w, r.chunk);
+  if (rc != PDFS_OK) return rc;
+  CK(c, hipMemcpyAsync(c->h_st, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, c->stream));
+  CK(c, hipEventRecord(c->chunk_done, c->stream));
+  r.chunk_w64 = w64;
+  r.pending = true;
+  return PDFS_OK;
+}
+
+int32_t run_poll(pdfs_ctx* c, bool wait, bool* ready, bool* done) {
+  Run& r = c->run;
+  *ready = false;
+  *done = !r.active;
+  if (!r.active || !r.pending) return PDFS_OK;
+  if (wait) {
+    CK(c, hipEventSynchronize(c->chunk_done));
+  } else {
+    const hipError_t q = hipEventQuery(c->chunk_done);
+    if (q == hipErrorNotReady) return PDFS_OK;
+    CK(c, q);
+  }
+  *ready = true;
+  r.pending = false;
+  const RoundState& st = *c->h_st;
+  if (c->time_kernels) {
+    const int ran = st.executed - r.executed_before;
+    for (int k = 0; k < ran && k < r.chunk; ++k) {
+      float ms = 0.f;
+      if (r.h >= 2) {
+        CK(c, hipEventElapsedTime(&ms, c->ev[k][0], c->ev[k][1]));
+        c->kernel_ns[0] += (int64_t)(ms * 1e6);
+        c->kernel_launches[0] += 1;
+      }
+      if (r.h >= 3) {
+        CK(c, hipEventElapsedTime(&ms, c->ev[k][2], c->ev[k][3]));
+        c->kernel_ns[1] += (int64_t)(ms * 1e6);
+        c->kernel_launches[1] += 1;
+      }
+    }
+  }
+  r.executed_before = st.executed;
+  if (st.overflow & 2) {
+    r.active = false;
+    return fail(c, PDFS_ERR_DEVICE, "corrupt per-wave result slot");
+  }
+  if (st.overflow) {
+    r.active = false;
+    return fail(c, PDFS_ERR_OUT_OF_MEMORY, "pair or item list capacity exceeded");
+  }
+  if (st.executed > c->n_tumor + 2) {
+    r.active = false;
+    return fail(c, PDFS_ERR_DEVICE, "greedy loop did not stop");
+  }
+  if (st.done) {
+    r.active = false;
+    *done = true;
+    return PDFS_OK;
+  }
+  r.n_unc = c->n_tumor - st.covered;
+  r.chunk = r.chunk * 2 < kMaxChunk ? r.chunk * 2 : kMaxChunk;
+  return PDFS_OK;
+}
+
+int32_t run_blocking(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int max_rounds,
+                     int n_unc) {
+  int32_t rc = run_start(c, h, p, q, target, max_rounds, n_unc);
+  while (rc == PDFS_OK) {
+    rc = run_enqueue(c);
+    if (rc != PDFS_OK) break;
+    bool ready = false, done = false;
+    rc = run_poll(c, true, &ready, &done);
+    if (done) break;
+  }
+  c->run.active = false;
+  return rc;
+}
+
+}  // namespace pdfs
+
+namespace pdfs {
 
 void begin_stats(pdfs_ctx* c, pdfs_stats* st) {
   if (st) memset(st, 0, sizeof(*st));
@@ -228,12 +311,28 @@ void begin_stats(pdfs_ctx* c, pdfs_stats* st) {
   c->kernel_launches[0] = c->kernel_launches[1] = 0;
 }
 
-void end_stats(pdfs_ctx* c, pdfs_stats* st) {
+void end_stats(pdfs_ctx* c, pdfs_stats* st, std::chrono::steady_clock::time_point t0) {
   if (!st) return;
+  const RoundState& r = *c->h_st;
+  for (int l = 0; l <= PDFS_MAX_H; ++l) {
+    st->visited[l] = r.tot.visited[l];
+    st->nonempty[l] = r.tot.nonempty[l];
+    st->bound_pruned[l] = r.tot.bound_pruned[l];
+  }
+  st->rounds = r.rounds;
+  st->pair_macs = r.tx_pair_macs;
+  st->dfs_visits[3] = r.tx_vis3;
+  st->dfs_visits[4] = r.tx_vis4;
+  st->dfs_visit_words3 = r.tx_vis_words3;
+  st->dfs_visit_words4 = r.tx_vis_words4;
+  st->dfs_leaves = r.tx_leaves;
+  st->dfs_fp_leaves = r.tx_fp_leaves;
   for (int i = 0; i < 2; ++i) {
     st->kernel_ns[i] = c->kernel_ns[i];
     st->kernel_launches[i] = c->kernel_launches[i];
   }
+  st->ns_total = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                     std::chrono::steady_clock::now() - t0).count();
 }
 
 void fill_combo(pdfs_combo* o, const RoundRecord& r, int h) {
@@ -247,6 +346,10 @@ void fill_combo(pdfs_combo* o, const RoundRecord& r, int h) {
   o->uncovered_before = r.uncovered_before;
   o->score_num = r.score_num; o->score_den = r.score_den;
 }
+
+}  // namespace pdfs
+
+namespace pdfs {
 
 int32_t check_call(pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
   if (!c) return PDFS_ERR_INVALID_ARG;
@@ -277,6 +380,54 @@ bool mask_pad_ok(const uint64_t* U, int n, int wt) {
   return true;
 }
 
+
+int32_t set_uncovered(pdfs_ctx* c, const uint64_t* mask) {
+  if (mask) {
+    if (!mask_pad_ok(mask, c->n_tumor, c->wt))
+      return fail(c, PDFS_ERR_INVALID_ARG, "uncovered mask has bits past n_tumor");
+    CK(c, hipMemcpyAsync(c->U, mask, sizeof(uint64_t) * c->wt, hipMemcpyHostToDevice,
+                         c->stream));
+    return popcount_mask(mask, c->wt);
+  }
+  CK(c, launch_fill_u(c->U, c->wt, c->n_tumor, c->stream));
+  return c->n_tumor;
+}
+
+int32_t run_records(pdfs_ctx* c, pdfs_combo* out, int32_t cap, int32_t* rounds) {
+  *rounds = c->h_st->rounds;
+  const int n = *rounds < cap ? *rounds : cap;
+  if (n > 0 && out) {
+    std::vector<RoundRecord> recs((size_t)n);
+    CK(c, hipMemcpyAsync(recs.data(), c->recs, sizeof(RoundRecord) * recs.size(),
+                         hipMemcpyDeviceToHost, c->stream));
+    CK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < n; ++i) fill_combo(&out[i], recs[i], c->run.h);
+  }
+  return PDFS_OK;
+}
+
+size_t footprint_bytes(int G, int n_tumor, int n_normal, int nA_max, int h, int prune_mode) {
+  const size_t wt = (size_t)words(n_tumor), wn = (size_t)(n_normal > 0 ? words(n_normal) : 1);
+  const size_t rows = (size_t)((nA_max + 127) / 128 * 128 + 128);
+  const int w64max = dfs_row_words((int)wt);
+  size_t b = (size_t)G * (wt + wn) * 8 + (size_t)G * 13 + (size_t)n_tumor * 8;
+  b += rows * (2 * (size_t)w64max * 4 + kMaxWN32 * 4 + (size_t)unpacked_row_bytes(w64max));
+  b += (size_t)kSlotPhases * kSlotsPerPhase * sizeof(Slot);
+  b += (size_t)kSlotPhases * kPersistBlocks * kTallyN * 8;
+  if (h >= 3) {
+    size_t pairs = (size_t)nA_max * (nA_max > 0 ? nA_max - 1 : 0) / 2;
+    if (pairs < 64) pairs = 64;
+    size_t items = 2 * ((pairs + kPairBatch - 1) / kPairBatch);
+    if (items < ((size_t)1 << 20)) items = (size_t)1 << 20;
+    b += pairs * 8 * (prune_mode == PDFS_PRUNE_BOUND ? 2 : 1) + items * sizeof(Item);
+  }
+  if (h == 2) b += rows * (size_t)unpacked_row_bytes((int)wn);
+  return b + ((size_t)1 << 20);
+}
+
+}  // namespace pdfs
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -308,6 +459,31 @@ int32_t pdfs_set_prune_mode(pdfs_ctx* c, int32_t mode) {
 }
 
 int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out) {
+  return create_ctx(m, opt, out, nullptr, false);
+}
+
+void pdfs_destroy(pdfs_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  // A context with stream-ordered memory frees in stream order; its own work
+  // must be finished (callers destroy it once its run has stopped), but other
+  // work sharing the stream need not be waited for.
+  if (c->run.pending || !c->async_alloc) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+  }
+  release(c);
+  delete c;
+}
+
+}  // extern "C"
+
+namespace pdfs {
+
+const std::string& create_error() { return g_create_error; }
+
+int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out,
+                   RoundState* pinned_state, bool async_alloc) {
   if (!out) return fail(nullptr, PDFS_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!m) return fail(nullptr, PDFS_ERR_INVALID_ARG, "matrix is NULL");
@@ -331,6 +507,7 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   pdfs_ctx* c = new pdfs_ctx();
   c->device = opt ? opt->device : 0;
   c->stream = opt ? static_cast<hipStream_t>(opt->stream) : nullptr;
+  c->async_alloc = async_alloc && c->stream != nullptr;
   c->prune_mode = mode;
   c->time_kernels = opt && (opt->flags & PDFS_OPT_TIME_KERNELS);
   c->G = m->G; c->n_tumor = m->n_tumor; c->n_normal = m->n_normal;
@@ -354,7 +531,10 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   hipStream_t s = c->stream;
   const int G = m->G;
   if (c->time_kernels)
-    for (hipEvent_t& e : c->ev) CKC(hipEventCreate(&e));
+    for (auto& row : c->ev)
+      for (hipEvent_t& e : row) CKC(hipEventCreate(&e));
+  CKC(hipEventCreateWithFlags(&c->chunk_done, hipEventDisableTiming));
+  c->use_graphs = c->stream != nullptr && opt && (opt->flags & PDFS_OPT_GRAPHS);
 
   // Stage the caller's matrices on the device (strided as given).
   const uint64_t* dT = m->tumor;
@@ -362,12 +542,12 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   uint64_t* stageT = nullptr;
   uint64_t* stageN = nullptr;
   if (!m->on_device) {
-    CKC(dalloc(&stageT, (size_t)G * m->tumor_stride_words));
+    CKC(dalloc(c, &stageT, (size_t)G * m->tumor_stride_words));
     CKC(hipMemcpyAsync(stageT, m->tumor, (size_t)G * m->tumor_stride_words * 8,
                        hipMemcpyHostToDevice, s));
     dT = stageT;
     if (m->n_normal > 0) {
-      CKC(dalloc(&stageN, (size_t)G * m->normal_stride_words));
+      CKC(dalloc(c, &stageN, (size_t)G * m->normal_stride_words));
       CKC(hipMemcpyAsync(stageN, m->normal, (size_t)G * m->normal_stride_words * 8,
                          hipMemcpyHostToDevice, s));
       dN = stageN;
@@ -375,20 +555,21 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   }
   if (m->n_normal == 0) dN = nullptr;
   auto free_stage = [&]() {
-    if (stageT) (void)hipFree(stageT);
-    if (stageN) (void)hipFree(stageN);
+    dfree(c, stageT);
+    dfree(c, stageN);
+    stageT = stageN = nullptr;
   };
 
   // Pad bits must be zero.
   int* d_bad = nullptr;
-  CKC(dalloc(&d_bad, 1));
+  CKC(dalloc(c, &d_bad, 1));
   CKC(hipMemsetAsync(d_bad, 0, sizeof(int), s));
   CKC(launch_check_pad(dT, m->tumor_stride_words, G, m->n_tumor, d_bad, s));
   if (dN) CKC(launch_check_pad(dN, m->normal_stride_words, G, m->n_normal, d_bad, s));
   int bad = 0;
   CKC(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
   CKC(hipStreamSynchronize(s));
-  (void)hipFree(d_bad);
+  dfree(c, d_bad);
   if (bad) {
     free_stage();
     c->err = "nonzero bits past the sample count";
@@ -398,20 +579,20 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   // Sparsest-first order: stable radix sort of the combined counts.
   uint32_t* counts = nullptr;   // [G] counts, then [G] ids
   uint32_t* counts_sorted = nullptr;
-  CKC(dalloc(&counts, 2 * (size_t)G));
-  CKC(dalloc(&counts_sorted, (size_t)G));
-  CKC(dalloc(&c->perm, (size_t)G));
+  CKC(dalloc(c, &counts, 2 * (size_t)G));
+  CKC(dalloc(c, &counts_sorted, (size_t)G));
+  CKC(dalloc(c, &c->perm, (size_t)G));
   CKC(launch_gene_counts(dT, m->tumor_stride_words, dN, m->normal_stride_words, G, wt, wn_in,
                          counts, s));
   size_t tmp_bytes = 0;
   CKC(sort_genes(counts, counts_sorted, reinterpret_cast<int32_t*>(counts + G), c->perm, G,
                  nullptr, &tmp_bytes, s));
   void* tmp = nullptr;
-  CKC(hipMalloc(&tmp, tmp_bytes + 256));
+  CKC(dmalloc(c, &tmp, tmp_bytes));
   CKC(sort_genes(counts, counts_sorted, reinterpret_cast<int32_t*>(counts + G), c->perm, G, tmp,
                  &tmp_bytes, s));
-  CKC(dalloc(&c->Ts, (size_t)G * wt));
-  CKC(dalloc(&c->Ns, (size_t)G * c->wn));
+  CKC(dalloc(c, &c->Ts, (size_t)G * wt));
+  CKC(dalloc(c, &c->Ns, (size_t)G * c->wn));
   CKC(launch_gather_sorted(dT, m->tumor_stride_words, dN, m->normal_stride_words, c->perm, G, wt,
                            c->wn, c->Ts, c->Ns, s));
   c->h_perm.resize(G);
@@ -420,23 +601,30 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   CKC(hipMemcpyAsync(h_counts.data(), counts_sorted, sizeof(uint32_t) * G,
                      hipMemcpyDeviceToHost, s));
   CKC(hipStreamSynchronize(s));
-  (void)hipFree(tmp);
-  (void)hipFree(counts);
-  (void)hipFree(counts_sorted);
+  dfree(c, tmp);
+  dfree(c, counts);
+  dfree(c, counts_sorted);
   free_stage();
 
   // Upper bound of the active list: genes with any tumour mutation.
-  CKC(dalloc(&c->U, (size_t)wt));
-  CKC(dalloc(&c->cols, (size_t)m->n_tumor));
-  CKC(dalloc(&c->act, (size_t)G));
-  CKC(dalloc(&c->flags, (size_t)G));
-  CKC(dalloc(&c->st, 1));
-  CKC(dalloc(&c->rec, 1));
-  CKC(dalloc(&c->slots, (size_t)kSlotPhases * kSlotsPerPhase));
-  CKC(dalloc(&c->hist, (size_t)kMaxCount + 1));
-  CKC(dalloc(&c->tallies, (size_t)kSlotPhases * kPersistBlocks * kTallyN));
-  CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_st), sizeof(RoundState), hipHostMallocDefault));
-  CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_rec), sizeof(RoundRecord), hipHostMallocDefault));
+  CKC(dalloc(c, &c->U, (size_t)wt));
+  CKC(dalloc(c, &c->cols, (size_t)m->n_tumor));
+  CKC(dalloc(c, &c->act, (size_t)G));
+  CKC(dalloc(c, &c->flags, (size_t)G));
+  CKC(dalloc(c, &c->st, 1));
+  c->rec_cap = m->n_tumor + 1;   // every found round covers at least one sample
+  CKC(dalloc(c, &c->recs, (size_t)c->rec_cap));
+  CKC(dalloc(c, &c->slots, (size_t)kSlotPhases * kSlotsPerPhase));
+  CKC(dalloc(c, &c->hist, (size_t)kMaxCount + 1));
+  CKC(dalloc(c, &c->tallies, (size_t)kSlotPhases * kPersistBlocks * kTallyN));
+  if (pinned_state) {
+    c->h_st = pinned_state;
+    c->own_h_st = false;
+  } else {
+    CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_st), sizeof(RoundState),
+                      hipHostMallocDefault));
+  }
+
   CKC(hipMemsetAsync(c->st, 0, sizeof(RoundState), s));
   CKC(launch_clear_slots(c->slots, kSlotPhases * kSlotsPerPhase, s));
   {
@@ -453,22 +641,17 @@ int32_t pdfs_create(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** ou
   }
   // row padding: whole 128-row MFMA block tiles
   const size_t rows = (size_t)((c->nA_max + 127) / 128 * 128 + 128);
-  CKC(dalloc(&c->TA, rows * 2 * (size_t)c->w64_max));
-  CKC(dalloc(&c->NA, rows * (size_t)kMaxWN32));
-  CKC(dalloc(&c->A8, rows * (size_t)unpacked_row_bytes(c->w64_max)));
+  CKC(dalloc(c, &c->TA, rows * 2 * (size_t)c->w64_max));
+  CKC(dalloc(c, &c->NA, rows * (size_t)kMaxWN32));
+  CKC(dalloc(c, &c->A8, rows * (size_t)unpacked_row_bytes(c->w64_max)));
   *out = c;
   return PDFS_OK;
 #undef CKC
 }
 
-void pdfs_destroy(pdfs_ctx* c) {
-  if (!c) return;
-  (void)hipSetDevice(c->device);
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  else (void)hipDeviceSynchronize();
-  release(c);
-  delete c;
-}
+}  // namespace pdfs
+
+extern "C" {
 
 int32_t pdfs_best_combo(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q, const uint64_t* uncovered,
                         pdfs_combo* out, pdfs_stats* stats) {
@@ -477,30 +660,18 @@ int32_t pdfs_best_combo(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q, const ui
   if (!out) return fail(c, PDFS_ERR_INVALID_ARG, "out is NULL");
   auto t0 = std::chrono::steady_clock::now();
   begin_stats(c, stats);
-  int n_unc = c->n_tumor;
-  if (uncovered) {
-    if (!mask_pad_ok(uncovered, c->n_tumor, c->wt))
-      return fail(c, PDFS_ERR_INVALID_ARG, "uncovered mask has bits past n_tumor");
-    n_unc = popcount_mask(uncovered, c->wt);
-    CK(c, hipMemcpyAsync(c->U, uncovered, sizeof(uint64_t) * c->wt, hipMemcpyHostToDevice,
-                         c->stream));
-  } else {
-    CK(c, launch_fill_u(c->U, c->wt, c->n_tumor, c->stream));
-  }
   memset(out, 0, sizeof(*out));
+  const int32_t n_unc = set_uncovered(c, uncovered);
+  if (n_unc < 0) return n_unc;
   if (n_unc == 0) return PDFS_NO_COMBO;
-  rc = run_round(c, h, p, q, c->n_tumor + 1, n_unc);
+  // one round: the target is out of reach, the round cap is 1
+  rc = run_blocking(c, h, p, q, c->n_tumor + 1, 1, n_unc);
   if (rc != PDFS_OK) return rc;
-  add_counters(stats, *c->h_st, h);
-  if (stats) {
-    end_stats(c, stats);
-    stats->rounds = c->h_rec->found ? 1 : 0;
-    stats->ns_total = std::chrono::duration_cast<std::chrono::nanoseconds>(
-                          std::chrono::steady_clock::now() - t0).count();
-  }
-  if (!c->h_rec->found) return PDFS_NO_COMBO;
-  fill_combo(out, *c->h_rec, h);
-  return PDFS_OK;
+  end_stats(c, stats, t0);
+  int32_t rounds = 0;
+  rc = run_records(c, out, 1, &rounds);
+  if (rc != PDFS_OK) return rc;
+  return rounds < 1 ? PDFS_NO_COMBO : PDFS_OK;
 }
 
 int32_t pdfs_wsc_run(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q, int32_t target_covered,
@@ -514,40 +685,20 @@ int32_t pdfs_wsc_run(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q, int32_t tar
   begin_stats(c, stats);
   *n_out = 0;
   const int K = target_covered > 0 ? target_covered : c->n_tumor;
-  int n_unc = c->n_tumor;
-  if (initial_uncovered) {
-    if (!mask_pad_ok(initial_uncovered, c->n_tumor, c->wt))
-      return fail(c, PDFS_ERR_INVALID_ARG, "uncovered mask has bits past n_tumor");
-    n_unc = popcount_mask(initial_uncovered, c->wt);
-    CK(c, hipMemcpyAsync(c->U, initial_uncovered, sizeof(uint64_t) * c->wt,
-                         hipMemcpyHostToDevice, c->stream));
-  } else {
-    CK(c, launch_fill_u(c->U, c->wt, c->n_tumor, c->stream));
-  }
-  int rounds = 0;
-  while (c->n_tumor - n_unc < K && (max_rounds <= 0 || rounds < max_rounds) && n_unc > 0) {
-    rc = run_round(c, h, p, q, K, n_unc);
-    if (rc != PDFS_OK) return rc;
-    add_counters(stats, *c->h_st, h);
-    const RoundRecord& r = *c->h_rec;
-    if (!r.found) break;
-    if (r.tp <= 0 || r.tp > n_unc) return fail(c, PDFS_ERR_DEVICE, "round made no progress");
-    if (rounds < cap) fill_combo(&out[rounds], r, h);
-    ++rounds;
-    n_unc -= r.tp;
-  }
+  const int32_t n_unc = set_uncovered(c, initial_uncovered);
+  if (n_unc < 0) return n_unc;
+  rc = run_blocking(c, h, p, q, K, max_rounds > 0 ? max_rounds : 0, n_unc);
+  if (rc != PDFS_OK) return rc;
+  int32_t rounds = 0;
+  rc = run_records(c, out, cap, &rounds);
+  if (rc != PDFS_OK) return rc;
   *n_out = rounds;
   if (final_uncovered) {
     CK(c, hipMemcpyAsync(final_uncovered, c->U, sizeof(uint64_t) * c->wt, hipMemcpyDeviceToHost,
                          c->stream));
     CK(c, hipStreamSynchronize(c->stream));
   }
-  if (stats) {
-    end_stats(c, stats);
-    stats->rounds = rounds;
-    stats->ns_total = std::chrono::duration_cast<std::chrono::nanoseconds>(
-                          std::chrono::steady_clock::now() - t0).count();
-  }
+  end_stats(c, stats, t0);
   if (rounds > cap) return fail(c, PDFS_ERR_TRUNCATED, "more rounds than cap");
   return PDFS_OK;
 }

@@ -72,6 +72,12 @@ struct RoundState {
   Counters cnt;                    // this round's counters
   // work the DFS kernels had to do (active candidates only)
   unsigned long long x_vis3, x_vis4, x_leaves, x_fp_leaves;
+  // ---- whole-run state (set by k_run_begin, advanced by k_finish_round)
+  int32_t max_rounds;              // 0 = no cap
+  int32_t executed;                // rounds whose kernels ran (incl. a final empty one)
+  Counters tot;                    // counters summed over executed rounds
+  unsigned long long tx_vis3, tx_vis4, tx_leaves, tx_fp_leaves, tx_pair_macs;
+  unsigned long long tx_vis_words3, tx_vis_words4;   // visits x ceil(|U|/64)
 };
 
 // Per-block counter rows (summed by the round's finish kernel instead of
@@ -144,12 +150,15 @@ struct Work {
   Slot* slots;
   unsigned long long* tallies;      // [kSlotPhases][kPersistBlocks][kTallyN]
   RoundState* st;
-  RoundRecord* rec;
+  RoundRecord* recs;                // one record per found round
+  int32_t rec_cap;
   unsigned long long pair_cap;
   unsigned long long item_cap;
   int32_t w64;       // compacted tumour words per row used this round
   int32_t wn32;      // normal 32-bit words per row
   int32_t target;    // covered-count stop target
+  int32_t chunk;     // depth-3 candidates per main-phase DFS item
+  int32_t seed_n;    // bound mode: pairs expanded in the seed phase
 };
 
 // ---------------------------------------------------------------- launchers
@@ -179,5 +188,6 @@ hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, 
                                hipStream_t s);
 hipError_t launch_clear_slots(Slot* slots, int n, hipStream_t s);
 hipError_t launch_fill_u(uint64_t* U, int wt, int n, hipStream_t s);
+hipError_t launch_run_begin(const Problem& P, const Work& w, int max_rounds, hipStream_t s);
 
 }  // namespace pdfs

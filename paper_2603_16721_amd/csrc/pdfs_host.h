@@ -1,0 +1,118 @@
+// Host-side internals of libpdfs shared by the plain C ABI (pdfs_api.cpp) and
+// the batched / served front ends (pdfs_batch.cpp).  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pdfs.h"
+#include "pdfs_dev.h"
+
+namespace pdfs {
+
+int dfs_row_words(int n);
+
+// Rounds enqueued between two reads of the device state (the chunk grows from
+// 2 to this many).  Rounds queued past the stop are no-ops on the device.
+constexpr int kMaxChunk = 16;
+
+// Progress of one greedy run on a context, advanced without blocking.
+struct Run {
+  bool active = false;      // started and not finished
+  bool pending = false;     // a chunk is in flight
+  int h = 0;
+  uint32_t p = 1, q = 1;
+  int target = 0, max_rounds = 0;
+  int n_unc = 0;            // |U| known to the host (only shrinks)
+  int chunk = 2;
+  int chunk_w64 = 0;
+  int executed_before = 0;
+  int32_t status = PDFS_OK;
+};
+
+}  // namespace pdfs
+
+struct pdfs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int prune_mode = PDFS_PRUNE_BOUND;
+  int G = 0, n_tumor = 0, n_normal = 0, wt = 0, wn = 0;
+  int nA_max = 0;
+  int w64_max = 0;
+  uint64_t* Ts = nullptr;
+  uint64_t* Ns = nullptr;
+  int32_t* perm = nullptr;
+  uint64_t* U = nullptr;
+  int32_t* cols = nullptr;
+  int32_t* act = nullptr;
+  uint8_t* flags = nullptr;
+  uint32_t* TA = nullptr;
+  uint32_t* NA = nullptr;
+  int8_t* A8 = nullptr;
+  int8_t* N8 = nullptr;
+  unsigned long long* pairs = nullptr;
+  unsigned long long* work_pairs = nullptr;   // bound mode only
+  unsigned long long* seed_pairs = nullptr;
+  uint32_t* hist = nullptr;
+  unsigned long long pair_cap = 0;
+  pdfs::Item* items = nullptr;
+  unsigned long long item_cap = 0;
+  pdfs::Slot* slots = nullptr;
+  unsigned long long* tallies = nullptr;
+  pdfs::RoundState* st = nullptr;
+  pdfs::RoundRecord* recs = nullptr;   // device, rec_cap records
+  int rec_cap = 0;
+  pdfs::RoundState* h_st = nullptr;    // pinned
+  std::vector<int32_t> h_perm;
+  std::string err;
+  bool time_kernels = false;
+  bool use_graphs = false;             // replay one captured round per row width
+  int chunk_items = 256;               // depth-3 candidates per DFS work item
+  int seed_pairs_n = 256;              // bound mode: pairs expanded first
+  hipEvent_t ev[pdfs::kMaxChunk][4] = {};
+  hipEvent_t chunk_done = nullptr;
+  // per-call accumulation of the timed launches
+  int64_t kernel_ns[2] = {0, 0};
+  int32_t kernel_launches[2] = {0, 0};
+  pdfs::Run run;
+  // captured round graphs keyed by (h, w64, p, q, target, mode, chunk, seed)
+  std::map<std::tuple<int, int, uint32_t, uint32_t, int, int, int, int>, hipGraphExec_t> graphs;
+  size_t bytes = 0;                    // device bytes held (admission accounting)
+  bool async_alloc = false;            // stream-ordered allocation (batched / served)
+  bool own_h_st = true;                // h_st allocated by the context
+};
+
+namespace pdfs {
+
+int32_t ctx_fail(pdfs_ctx* c, int32_t code, const std::string& msg);
+// pdfs_create with two internal options: pinned_state (a caller-owned pinned
+// RoundState, or NULL) and stream-ordered allocation on opt->stream.
+int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out,
+                   RoundState* pinned_state, bool async_alloc);
+void begin_stats(pdfs_ctx* c, pdfs_stats* st);
+void end_stats(pdfs_ctx* c, pdfs_stats* st, std::chrono::steady_clock::time_point t0);
+const std::string& create_error();
+// Starts a greedy run (U must already hold the starting mask on c->stream).
+int32_t run_start(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int max_rounds,
+                  int n_unc);
+// Enqueues the next chunk of rounds and the state read-back; non-blocking.
+int32_t run_enqueue(pdfs_ctx* c);
+// Checks a pending chunk (waits for it when wait is true).  *done is set when
+// the run has stopped; *ready when the chunk was processed.
+int32_t run_poll(pdfs_ctx* c, bool wait, bool* ready, bool* done);
+// Blocking run: start + chunks until done.
+int32_t run_blocking(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int max_rounds,
+                     int n_unc);
+// Copies up to cap round records of the finished run into out; returns rounds.
+int32_t run_records(pdfs_ctx* c, pdfs_combo* out, int32_t cap, int32_t* rounds);
+int32_t check_call(pdfs_ctx* c, int h, uint32_t p, uint32_t q);
+// Sets U from a host mask (NULL = all samples); returns |U| or -1.
+int32_t set_uncovered(pdfs_ctx* c, const uint64_t* mask);
+// Device bytes a context of this shape will hold (admission control).
+size_t footprint_bytes(int G, int n_tumor, int n_normal, int nA_max, int h, int prune_mode);
+
+}  // namespace pdfs

@@ -68,7 +68,12 @@ class pdfs_stats(ctypes.Structure):
 
 
 EXPORTS = ["pdfs_create", "pdfs_destroy", "pdfs_set_prune_mode", "pdfs_best_combo",
-           "pdfs_wsc_run", "pdfs_strerror", "pdfs_last_error"]
+           "pdfs_wsc_run", "pdfs_strerror", "pdfs_last_error",
+           "pdfs_batch_create", "pdfs_batch_run", "pdfs_batch_destroy",
+           "pdfs_server_create", "pdfs_server_submit", "pdfs_server_poll", "pdfs_server_drain",
+           "pdfs_server_destroy"]
+PDFS_OPT_GRAPHS = 2
+PDFS_OPT_AUTOTUNE = 4
 
 
 def _load():
@@ -94,6 +99,29 @@ def _load():
     L.pdfs_strerror.restype = ctypes.c_char_p
     L.pdfs_last_error.argtypes = [P]
     L.pdfs_last_error.restype = ctypes.c_char_p
+    PC = ctypes.POINTER(pdfs_combo)
+    L.pdfs_batch_create.argtypes = [ctypes.POINTER(pdfs_matrix), i32, ctypes.POINTER(pdfs_options),
+                                    ctypes.POINTER(P)]
+    L.pdfs_batch_create.restype = i32
+    L.pdfs_batch_run.argtypes = [P, ctypes.POINTER(i32), u32, u32, ctypes.POINTER(i32),
+                                 ctypes.POINTER(PC), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                 ctypes.POINTER(pdfs_stats)]
+    L.pdfs_batch_run.restype = i32
+    L.pdfs_batch_destroy.argtypes = [P]
+    L.pdfs_batch_destroy.restype = None
+    L.pdfs_server_create.argtypes = [ctypes.POINTER(pdfs_options), ctypes.c_uint64, i32,
+                                     ctypes.POINTER(P)]
+    L.pdfs_server_create.restype = i32
+    L.pdfs_server_submit.argtypes = [P, ctypes.POINTER(pdfs_matrix), i32, u32, u32, i32,
+                                     ctypes.POINTER(ctypes.c_uint64)]
+    L.pdfs_server_submit.restype = i32
+    L.pdfs_server_poll.argtypes = [P, ctypes.c_uint64, PC, i32, ctypes.POINTER(i32),
+                                   ctypes.POINTER(ctypes.c_int64)]
+    L.pdfs_server_poll.restype = i32
+    L.pdfs_server_drain.argtypes = [P]
+    L.pdfs_server_drain.restype = i32
+    L.pdfs_server_destroy.argtypes = [P]
+    L.pdfs_server_destroy.restype = None
     return L
 
 
@@ -256,3 +284,92 @@ class Solver:
     def wsc(self, h, p=1, q=10, target=0, max_rounds=0, initial_uncovered=None, cap=4096):
         return pdfs_wsc_run(self.ctx, h, p, q, target, max_rounds, initial_uncovered, cap,
                             n_tumor=self.n_tumor)
+
+
+def pdfs_batch_create(instances, prune_mode="bound", device=0, autotune=False):
+    """instances: list of (tumor, normal, n_tumor, n_normal) host arrays.  Returns a handle."""
+    mats, keep = [], []
+    for (T, N, nt, nn) in instances:
+        m, k = _matrix_arg(T, N, nt, nn)
+        mats.append(m)
+        keep.append(k)
+    arr = (pdfs_matrix * len(mats))(*mats)
+    mode = PRUNE_MODES[prune_mode] if isinstance(prune_mode, str) else int(prune_mode)
+    opt = pdfs_options(prune_mode=mode, device=device, stream=None,
+                       flags=PDFS_OPT_AUTOTUNE if autotune else 0)
+    out = ctypes.c_void_p()
+    rc = lib.pdfs_batch_create(arr, len(mats), ctypes.byref(opt), ctypes.byref(out))
+    del keep
+    if rc != PDFS_OK:
+        raise PdfsError(rc, lib.pdfs_last_error(None).decode())
+    return out.value
+
+
+def pdfs_batch_run(batch, hs, alpha_p, alpha_q, targets=None, caps=None, n_tumors=None):
+    """Returns (list of per-instance round lists, aggregate stats dict)."""
+    n = len(hs)
+    if caps is None:
+        caps = [(nt + 1) if n_tumors else 4096 for nt in (n_tumors or [0] * n)]
+    bufs = [(pdfs_combo * max(1, c))() for c in caps]
+    outs = (ctypes.POINTER(pdfs_combo) * n)(*[ctypes.cast(b, ctypes.POINTER(pdfs_combo))
+                                               for b in bufs])
+    h_arr = (ctypes.c_int32 * n)(*hs)
+    t_arr = (ctypes.c_int32 * n)(*(targets or [0] * n))
+    c_arr = (ctypes.c_int32 * n)(*caps)
+    n_out = (ctypes.c_int32 * n)()
+    st = pdfs_stats()
+    rc = lib.pdfs_batch_run(batch, h_arr, alpha_p, alpha_q, t_arr, outs, c_arr, n_out,
+                            ctypes.byref(st))
+    if rc != PDFS_OK:
+        raise PdfsError(rc)
+    res = [[combo_dict(bufs[i][k]) for k in range(n_out[i])] for i in range(n)]
+    return res, stats_dict(st, max(hs))
+
+
+def pdfs_batch_destroy(batch):
+    lib.pdfs_batch_destroy(batch)
+
+
+def pdfs_server_create(prune_mode="bound", device=0, hbm_budget_bytes=0, max_active=8):
+    mode = PRUNE_MODES[prune_mode] if isinstance(prune_mode, str) else int(prune_mode)
+    opt = pdfs_options(prune_mode=mode, device=device, stream=None, flags=0)
+    out = ctypes.c_void_p()
+    rc = lib.pdfs_server_create(ctypes.byref(opt), hbm_budget_bytes, max_active,
+                                ctypes.byref(out))
+    if rc != PDFS_OK:
+        raise PdfsError(rc)
+    return out.value
+
+
+def pdfs_server_submit(server, tumor, normal, n_tumor, n_normal, h, alpha_p, alpha_q, target=0):
+    m, keep = _matrix_arg(tumor, normal, n_tumor, n_normal)
+    ticket = ctypes.c_uint64(0)
+    rc = lib.pdfs_server_submit(server, ctypes.byref(m), h, alpha_p, alpha_q, target,
+                                ctypes.byref(ticket))
+    del keep
+    if rc != PDFS_OK:
+        raise PdfsError(rc)
+    return ticket.value
+
+
+def pdfs_server_poll(server, ticket, cap=4096):
+    """Returns None while pending, else (rounds list, latency seconds)."""
+    buf = (pdfs_combo * max(1, cap))()
+    n_out = ctypes.c_int32(0)
+    lat = ctypes.c_int64(0)
+    rc = lib.pdfs_server_poll(server, ticket, buf, cap, ctypes.byref(n_out), ctypes.byref(lat))
+    if rc == PDFS_PENDING:
+        return None
+    if rc != PDFS_OK:
+        raise PdfsError(rc)
+    return [combo_dict(buf[k]) for k in range(n_out.value)], lat.value * 1e-9
+
+
+def pdfs_server_drain(server):
+    rc = lib.pdfs_server_drain(server)
+    if rc != PDFS_OK:
+        raise PdfsError(rc)
+
+
+def pdfs_server_destroy(server):
+    lib.pdfs_server_destroy(server)

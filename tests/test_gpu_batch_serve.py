@@ -1,0 +1,156 @@
+"""Batched and served front ends: every result equals the oracle's (and the
+plain path's), alone or in a mix; admission by device memory; repeated graph
+replays give the same results."""
+import json
+import os
+import time
+
+import pytest
+
+from paper_2603_16721_amd import synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def pdfs():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_16721_amd import pdfs as binding
+    return binding
+
+
+def _golden(kind):
+    with open(os.path.join(HERE, "golden", f"{kind}_oracle.json")) as f:
+        return json.load(f)["instances"]
+
+
+def _compact(rounds):
+    return [[*r["genes"], r["tp"], r["fp"], r["score_num"]] for r in rounds]
+
+
+def _batch(pdfs, idx, autotune=False, mode="bound"):
+    insts = [synth.batched_instance(i) for i in idx]
+    packed = [(I.packed(), I) for I in insts]
+    b = pdfs.pdfs_batch_create([(T, N, I.n_tumor, I.n_normal) for (T, N), I in packed], mode,
+                               autotune=autotune)
+    return b, insts
+
+
+def test_batched_all_instances_match_oracle(pdfs):
+    gold = _golden("batched")
+    b, insts = _batch(pdfs, range(32))
+    try:
+        res, st = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
+                                      n_tumors=[I.n_tumor for I in insts])
+        for i, I in enumerate(insts):
+            assert _compact(res[i]) == gold[str(i)]["rounds"], i
+        # the same batch again: replays of the captured rounds
+        res2, _ = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
+                                      n_tumors=[I.n_tumor for I in insts])
+        assert [_compact(r) for r in res2] == [_compact(r) for r in res]
+    finally:
+        pdfs.pdfs_batch_destroy(b)
+    assert st["rounds"] == sum(len(gold[str(i)]["rounds"]) for i in range(32))
+
+
+def test_batched_autotune_and_empty_mode_same_results(pdfs):
+    gold = _golden("batched")
+    idx = [0, 5, 7, 12, 14, 20, 24, 28]   # small instances: quick in empty mode too
+    for mode, tune in (("bound", True), ("empty", False)):
+        b, insts = _batch(pdfs, idx, autotune=tune, mode=mode)
+        try:
+            res, _ = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
+                                         n_tumors=[I.n_tumor for I in insts])
+        finally:
+            pdfs.pdfs_batch_destroy(b)
+        for k, i in enumerate(idx):
+            assert _compact(res[k]) == gold[str(i)]["rounds"], (mode, i)
+
+
+def test_batched_equals_plain_path(pdfs):
+    for i in (1, 9, 30):
+        I = synth.batched_instance(i)
+        T, N = I.packed()
+        with pdfs.Solver(T, N, I.n_tumor, I.n_normal, "bound") as s:
+            plain, _, _ = s.wsc(I.h, 1, 10)
+        b, insts = _batch(pdfs, [i])
+        try:
+            res, _ = pdfs.pdfs_batch_run(b, [I.h], 1, 10, n_tumors=[I.n_tumor])
+        finally:
+            pdfs.pdfs_batch_destroy(b)
+        assert _compact(res[0]) == _compact(plain)
+
+
+def _serve(pdfs, js, max_active=8, one_at_a_time=False, budget=0):
+    srv = pdfs.pdfs_server_create("bound", 0, budget, max_active)
+    out = {}
+    try:
+        reqs = {j: synth.served_request(j) for j in js}
+        tickets = {}
+        for j in js:
+            I = reqs[j]
+            T, N = I.packed()
+            tickets[j] = pdfs.pdfs_server_submit(srv, T, N, I.n_tumor, I.n_normal, I.h, 1, 10)
+            if one_at_a_time:
+                while True:
+                    r = pdfs.pdfs_server_poll(srv, tickets[j], cap=I.n_tumor + 1)
+                    if r is not None:
+                        out[j] = r
+                        break
+                    time.sleep(0.001)
+        deadline = time.time() + 300
+        while len(out) < len(js):
+            for j in js:
+                if j in out:
+                    continue
+                r = pdfs.pdfs_server_poll(srv, tickets[j], cap=reqs[j].n_tumor + 1)
+                if r is not None:
+                    out[j] = r
+            assert time.time() < deadline, "served requests did not finish"
+            time.sleep(0.002)
+    finally:
+        pdfs.pdfs_server_destroy(srv)
+    return out
+
+
+def test_served_sample_matches_oracle(pdfs):
+    gold = _golden("served")
+    js = [int(j) for j in gold]
+    out = _serve(pdfs, js)
+    for j in js:
+        rounds, lat = out[j]
+        assert _compact(rounds) == gold[str(j)]["rounds"], j
+        assert lat > 0
+
+
+def test_served_alone_equals_mix(pdfs):
+    js = [3, 11, 42, 77, 105, 160, 199]
+    alone = _serve(pdfs, js, max_active=1, one_at_a_time=True)
+    mix = _serve(pdfs, js, max_active=8)
+    for j in js:
+        assert _compact(alone[j][0]) == _compact(mix[j][0]), j
+
+
+def test_server_admission_by_memory(pdfs):
+    I = synth.served_request(0)
+    T, N = I.packed()
+    srv = pdfs.pdfs_server_create("bound", 0, 1 << 20, 4)   # 1 MiB budget: too small
+    try:
+        with pytest.raises(pdfs.PdfsError) as e:
+            pdfs.pdfs_server_submit(srv, T, N, I.n_tumor, I.n_normal, I.h, 1, 10)
+        assert e.value.code == pdfs.PDFS_ERR_OUT_OF_MEMORY
+    finally:
+        pdfs.pdfs_server_destroy(srv)
+    # a budget that holds one or two of these requests: the rest queue, all finish
+    js = [1, 2, 4]
+    out = _serve(pdfs, js, max_active=4, budget=1 << 30)
+    assert sorted(out) == js
+    with pytest.raises(pdfs.PdfsError):
+        srv = pdfs.pdfs_server_create("bound", 0, 0, 2)
+        try:
+            pdfs.pdfs_server_poll(srv, 12345)
+        finally:
+            pdfs.pdfs_server_destroy(srv)
