@@ -75,6 +75,113 @@ def cpu_baseline(inst, T, N, every=20):
                        f"{leaves} leaves in {dt:.1f} s")}
 
 
+def _gen_request(j):
+    from paper_2603_16721_amd import synth
+    I = synth.served_request(j)
+    T, N = I.packed()
+    return j, T, N, I.n_tumor, I.n_normal, I.h
+
+
+def _gen_batched(i):
+    from paper_2603_16721_amd import synth
+    I = synth.batched_instance(i)
+    T, N = I.packed()
+    return i, T, N, I.n_tumor, I.n_normal, I.h
+
+
+def _pool_map(fn, items):
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(min(16, max(1, (os.cpu_count() or 2) - 1))) as pool:
+        return pool.map(fn, items)
+
+
+def bench_batched(pdfs, data):
+    """32 instances: serially through the plain path vs one batched run."""
+    import torch
+    hs = [d[5] for d in data]
+    # plain path: one context per instance, solved one after another
+    plain_ms = 0.0
+    plain_rounds = []
+    for (_, T, N, nt, nn, h) in data:
+        with pdfs.Solver(T, N, nt, nn, "bound") as s:
+            s.wsc(h, 1, 10)                        # warm (allocations)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r, _, _ = s.wsc(h, 1, 10)
+            plain_ms += 1e3 * (time.perf_counter() - t)
+            plain_rounds.append([(x["genes"], x["tp"], x["fp"]) for x in r])
+    b = pdfs.pdfs_batch_create([(T, N, nt, nn) for (_, T, N, nt, nn, _) in data], "bound",
+                               autotune=True)
+    try:
+        ncap = [nt + 1 for (_, _, _, nt, _, _) in data]
+        pdfs.pdfs_batch_run(b, hs, 1, 10, n_tumors=ncap)   # warm + tune
+        times = []
+        for _ in range(3):
+            t = time.perf_counter()
+            res, st = pdfs.pdfs_batch_run(b, hs, 1, 10, n_tumors=ncap)
+            times.append(1e3 * (time.perf_counter() - t))
+    finally:
+        pdfs.pdfs_batch_destroy(b)
+    same = [[(x["genes"], x["tp"], x["fp"]) for x in r] for r in res] == plain_rounds
+    batched_ms = min(times)
+    return {"instances": 32, "plain_serial_ms": plain_ms, "batched_ms": batched_ms,
+            "speedup": plain_ms / batched_ms, "rounds": st["rounds"], "same_results": same,
+            "mode": "bound"}
+
+
+def bench_served(pdfs, n_req, speed, data):
+    """The seeded Poisson request stream (mean 20 req/s, scaled by `speed`), h in
+    {2,3,4} at 3:5:2: continuous batching vs the plain path serving the same
+    arrivals one at a time."""
+    from paper_2603_16721_amd import synth
+    import numpy as np
+    arrivals = synth.served_arrivals()[:n_req] / speed
+
+    # plain path: one request at a time, in arrival order
+    lat_plain = []
+    t0 = time.perf_counter()
+    for j, (_, T, N, nt, nn, h) in enumerate(data):
+        now = time.perf_counter() - t0
+        if now < arrivals[j]:
+            time.sleep(arrivals[j] - now)
+        with pdfs.Solver(T, N, nt, nn, "bound") as s:
+            s.wsc(h, 1, 10)
+        lat_plain.append(time.perf_counter() - t0 - arrivals[j])
+    span_plain = time.perf_counter() - t0
+
+    srv = pdfs.pdfs_server_create("bound", 0, 0, 8)
+    lat_srv = [None] * n_req
+    try:
+        tickets = []
+        t0 = time.perf_counter()
+        j = 0
+        while j < n_req or any(l is None for l in lat_srv):
+            now = time.perf_counter() - t0
+            while j < n_req and arrivals[j] <= now:
+                (_, T, N, nt, nn, h) = data[j]
+                tickets.append(pdfs.pdfs_server_submit(srv, T, N, nt, nn, h, 1, 10))
+                j += 1
+            for k, tk in enumerate(tickets):
+                if lat_srv[k] is None:
+                    r = pdfs.pdfs_server_poll(srv, tk, cap=data[k][3] + 1)
+                    if r is not None:
+                        lat_srv[k] = r[1]
+            time.sleep(0.0005)
+        span_srv = time.perf_counter() - t0
+    finally:
+        pdfs.pdfs_server_destroy(srv)
+
+    def pct(x, q):
+        return float(np.percentile(np.asarray(x) * 1e3, q))
+    return {"requests": n_req, "rate_req_per_s": 20.0 * speed,
+            "served": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99),
+                       "solves_per_s": n_req / span_srv},
+            "plain_one_at_a_time": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
+                                    "solves_per_s": n_req / span_plain},
+            "mode": "bound", "latency": "submission to result, seconds of wall time"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,11 +191,22 @@ def main():
     ap.add_argument("--bound-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-every", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=400)
+    ap.add_argument("--served-speed", type=float, default=1.0,
+                    help="arrival-rate multiplier of the 20 req/s stream")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; multi-GPU sharding of the search is not "
               "built (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    # inputs of the batched and served workloads, generated in worker
+    # processes before this process touches the GPU
+    data_b = None if args.no_batched else sorted(_pool_map(_gen_batched, range(32)))
+    data_s = None if args.no_served else sorted(_pool_map(_gen_request,
+                                                          range(args.served_requests)))
 
     import numpy as np
     import torch
@@ -183,6 +301,12 @@ def main():
                        "avg_launch_ms": pair_ns / max(1, sum(s["kernel_launches"][0]
                                                              for s in stats)) * 1e-6},
     }
+    if not args.no_batched:
+        print("[bench] batched: 32 instances, plain serial vs batched", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(pdfs, data_b)
+    if not args.no_served:
+        print(f"[bench] served: {args.served_requests} requests", file=sys.stderr, flush=True)
+        out["served"] = bench_served(pdfs, args.served_requests, args.served_speed, data_s)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, T, N, args.cpu_every)
