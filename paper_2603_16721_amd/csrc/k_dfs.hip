@@ -100,6 +100,41 @@ __device__ __forceinline__ int popc_and_n(const uint32_t (&z)[kMaxWN32], cu32* r
   return c;
 }
 
+// sum over k of popcount(y[k] & r[k]) for a row already in (scalar) registers
+template <int W>
+__device__ __forceinline__ int popc_and_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+#pragma unroll
+  for (int k = 0; k < W; k += 4) {
+    c0 = bcnt_acc(y[k] & r[k], c0);
+    if (k + 1 < W) c1 = bcnt_acc(y[k + 1] & r[k + 1], c1);
+    if (k + 2 < W) c2 = bcnt_acc(y[k + 2] & r[k + 2], c2);
+    if (k + 3 < W) c3 = bcnt_acc(y[k + 3] & r[k + 3], c3);
+  }
+  return (int)(c0 + c1 + c2 + c3);
+}
+
+// Rows d .. d+KR-1 (clamped to `last`) into scalar registers.
+template <int W, int KR>
+__device__ __forceinline__ void load_rows(uint32_t (&r)[KR][W], cu32* base, int d, int last) {
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    const int dj = d + j < last ? d + j : last;
+#pragma unroll
+    for (int k = 0; k < W; ++k) r[j][k] = base[(size_t)dj * W + k];
+  }
+}
+
+// Makes `next` (the next row index) depend on the rows of the current group.
+// Scalar loads may complete out of order, so waiting for one waits for every
+// load in flight; tying the next group's addresses to the current group's
+// data places that wait before the next loads are issued, which then overlap
+// the current group's arithmetic.
+template <int W, int KR>
+__device__ __forceinline__ void after_arrival(int& next, const uint32_t (&r)[KR][W]) {
+  asm volatile("; rows arrived %1" : "+s"(next) : "s"(r[KR - 1][W - 1]));
+}
+
 __device__ __forceinline__ unsigned long long load_incumbent(RoundState* st) {
   return __hip_atomic_load(&st->incumbent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -196,12 +231,11 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
   }
   const bool zlive = live && znz != 0;
   if (live) tl.xv4 += (unsigned long long)(nA - 1 - c);
-  for (int d = c_first + 1; d < nA; ++d) {
-    cu32* row = TA + (size_t)d * W;
-    const int tp = popc_and<W>(y3, row);
+  auto step = [&](int d, const uint32_t (&row)[W]) {
+    const int tp = popc_and_r<W>(y3, row);
     const bool hit = live && d > c && tp > 0;
     const unsigned long long m = __ballot(hit);
-    if (m == 0) continue;
+    if (m == 0) return;
     tl.ne4 += __popcll(m);
     int fp = 0;
     if (__any(hit && zlive)) {
@@ -221,11 +255,37 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
         }
       }
     }
+  };
+  // candidates d stream through two register buffers of KR rows each: the
+  // next group is in flight while the current one is tested
+  constexpr int KR = W <= 16 ? 2 : 1;
+  int d = c_first + 1;
+  if (d < nA) {
+    uint32_t ra[KR][W], rb[KR][W];
+    load_rows<W, KR>(ra, TA, d, nA - 1);
+    for (;;) {
+      int dn = d + KR;
+      after_arrival<W, KR>(dn, ra);
+      load_rows<W, KR>(rb, TA, dn, nA - 1);
+#pragma unroll
+      for (int j = 0; j < KR; ++j)
+        if (d + j < nA) step(d + j, ra[j]);
+      d += KR;
+      if (d >= nA) break;
+      dn = d + KR;
+      after_arrival<W, KR>(dn, rb);
+      load_rows<W, KR>(ra, TA, dn, nA - 1);
+#pragma unroll
+      for (int j = 0; j < KR; ++j)
+        if (d + j < nA) step(d + j, rb[j]);
+      d += KR;
+      if (d >= nA) break;
+    }
   }
 }
 
 template <int H, int W64>
-__global__ __launch_bounds__(256) void k_dfs(Problem P, Work w, int phase) {
+__global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
   __shared__ uint32_t qbuf[kBlock / kWave][2 * kWave];
   RoundState* st = w.st;
