@@ -312,10 +312,12 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
   tl.init();
   unsigned long long inc = 0;
 
-  // Scheduling: wave g takes item g first (no atomic at launch); further
-  // items come from a shared cursor that counts past the first kWavesPerGrid.
-  // A plain read first, so that once the items are gone waves leave without
-  // queueing on the cursor's atomic.
+  // Scheduling: the grid is sized to what the device holds at once, so every
+  // wave starts at launch.  Wave g takes item g first (no atomic at launch);
+  // further items come from a shared cursor that counts past the first
+  // nwaves.  A plain read first, so that once the items are gone waves leave
+  // without queueing on the cursor's atomic.
+  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
   const uint32_t gw = blockIdx.x * (kBlock / kWave) + wib;
   bool first = true;
   for (;;) {
@@ -326,8 +328,8 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
     } else if (lane == 0) {
       const unsigned long long cur =
           __hip_atomic_load(&st->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (cur + kWavesPerGrid < nitems)
-        it = (uint32_t)(kWavesPerGrid + atomicAdd(&st->cursor, 1ull));
+      if (cur + nwaves < nitems)
+        it = (uint32_t)(nwaves + atomicAdd(&st->cursor, 1ull));
     }
     it = (uint32_t)uniform((int)it);
     if (it >= nitems) break;
@@ -456,6 +458,12 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
   v[kTXv4] = tl.xv4;
   v[kTXfp] = tl.xfp;
   block_tally_to(w.tallies + ((size_t)phase * kPersistBlocks + blockIdx.x) * kTallyN, v);
+  // slots and tally rows of blocks beyond a smaller grid read as empty
+  for (int vb = blockIdx.x + gridDim.x; vb < kPersistBlocks; vb += gridDim.x) {
+    if (threadIdx.x == 0) w.slots[(size_t)phase * kSlotsPerPhase + vb] = empty_slot();
+    if (threadIdx.x < kTallyN)
+      w.tallies[((size_t)phase * kPersistBlocks + vb) * kTallyN + threadIdx.x] = 0ull;
+  }
 }
 
 // Work items: batches of kPairBatch consecutive list pairs, each batch's
@@ -663,13 +671,35 @@ __global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
   if (threadIdx.x == 0 && bsum) atomicAdd(&st->cnt.bound_pruned[2], bsum);
 }
 
+// Blocks of one DFS instantiation resident per compute unit (register use
+// differs by row width), queried once.
+template <int H, int W64>
+int resident_blocks() {
+  static const int n = [] {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(&k_dfs<H, W64>), kBlock, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    return per_cu;
+  }();
+  return n;
+}
+
+template <int H, int W64>
+hipError_t launch_one(const Problem& P, const Work& w, int phase, hipStream_t s) {
+  int blocks = resident_blocks<H, W64>() * (P.n_cu > 0 ? P.n_cu : 1);
+  if (blocks > kPersistBlocks) blocks = kPersistBlocks;
+  k_dfs<H, W64><<<blocks, kBlock, 0, s>>>(P, w, phase);
+  return hipGetLastError();
+}
+
 template <int H>
 hipError_t dispatch(const Problem& P, const Work& w, int phase, hipStream_t s) {
-  dim3 g(kPersistBlocks), b(kBlock);
   switch (w.w64) {
 #define PDFS_CASE(n) \
   case n:            \
-    k_dfs<H, n><<<g, b, 0, s>>>(P, w, phase); break;
+    return launch_one<H, n>(P, w, phase, s);
     PDFS_CASE(1) PDFS_CASE(2) PDFS_CASE(3) PDFS_CASE(4) PDFS_CASE(5) PDFS_CASE(6)
     PDFS_CASE(7) PDFS_CASE(8) PDFS_CASE(10) PDFS_CASE(12) PDFS_CASE(14) PDFS_CASE(16)
     PDFS_CASE(18) PDFS_CASE(20)
@@ -677,7 +707,6 @@ hipError_t dispatch(const Problem& P, const Work& w, int phase, hipStream_t s) {
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace

@@ -111,6 +111,7 @@ Problem make_problem(const pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
   Problem P;
   P.G = c->G; P.n_tumor = c->n_tumor; P.n_normal = c->n_normal; P.wt = c->wt; P.wn = c->wn;
   P.h = h; P.p = (int32_t)p; P.q = (int32_t)q; P.mode = c->prune_mode;
+  P.n_cu = c->n_cu;
   return P;
 }
 
@@ -528,6 +529,7 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
     }                                                                                      \
   } while (0)
   CKC(hipSetDevice(c->device));
+  CKC(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
   hipStream_t s = c->stream;
   const int G = m->G;
   if (c->time_kernels)
@@ -630,7 +632,7 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   {
     Problem P;
     P.G = G; P.n_tumor = m->n_tumor; P.n_normal = m->n_normal; P.wt = wt; P.wn = c->wn;
-    P.h = 1; P.p = 1; P.q = 1; P.mode = mode;
+    P.h = 1; P.p = 1; P.q = 1; P.mode = mode; P.n_cu = c->n_cu;
     Work w = make_work(c, 1, 0);
     CKC(launch_fill_u(c->U, wt, m->n_tumor, s));
     CKC(launch_round_begin(P, w, s));

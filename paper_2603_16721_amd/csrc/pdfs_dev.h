@@ -127,6 +127,7 @@ struct Problem {
   int32_t h;
   int32_t p, q;
   int32_t mode;
+  int32_t n_cu;   // compute units of the device (sizes the persistent DFS grid)
 };
 
 // Round workspace pointers.

@@ -72,6 +72,7 @@ struct pdfs_ctx {
   bool time_kernels = false;
   bool use_graphs = false;             // replay one captured round per row width
   int chunk_items = 256;               // depth-3 candidates per DFS work item
+  int n_cu = 256;                      // compute units of the device
   int seed_pairs_n = 256;              // bound mode: pairs expanded first
   hipEvent_t ev[pdfs::kMaxChunk][4] = {};
   hipEvent_t chunk_done = nullptr;
