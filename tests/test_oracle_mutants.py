@@ -19,8 +19,8 @@ from tests.helpers import mask_of_bits
 MUTANTS = {
     "drop_tn_term": ("int64_t s = st->p * tp + st->q * tn;", "int64_t s = st->p * tp;"),
     "tn_sign": ("int64_t tn = st->n_normal - fp;", "int64_t tn = st->n_normal + fp;"),
-    "loop_bound_off_by_one": ("const int32_t hi = st->G - st->h + l - 1;",
-                              "const int32_t hi = st->G - st->h + l - 2;"),
+    "loop_bound_off_by_one": ("int32_t hi = st->G - st->h + l - 1;",
+                              "int32_t hi = st->G - st->h + l - 2;"),
     "tie_keeps_last": ("if (!st->found || s > st->best_s) {", "if (!st->found || s >= st->best_s) {"),
     "unsafe_bound": ("st->p * c + st->q * (int64_t)st->n_normal <= st->best_s",
                      "st->p * c + st->q * (int64_t)st->n_normal <= st->best_s + st->q"),
