@@ -133,9 +133,13 @@ typedef struct {
     int32_t reserved;
     int64_t ns_total;   /* host wall time of the call, nanoseconds */
     /* Filled when the context was created with PDFS_OPT_TIME_KERNELS:
-     * index 0 = int8-MFMA pair-table kernel, 1 = depth-first kernel. */
-    int64_t kernel_ns[2];        /* summed HIP-event durations            */
-    int32_t kernel_launches[2];  /* launches timed                        */
+     * index 0 = int8-MFMA pair-table kernel, 1 = depth-first stage (depths
+     * 3..h), 2 = the part of index 1 spent in the depth-4 tile kernel (h = 4
+     * under PDFS_PRUNE_EMPTY: depth-3 prefixes with long depth-4 candidate
+     * streams are listed, bucketed by their third gene and expanded in
+     * tiles; 0 otherwise). */
+    int64_t kernel_ns[3];        /* summed HIP-event durations            */
+    int32_t kernel_launches[3];  /* launches timed                        */
     /* Work the kernels had to do, counted inside them (always filled):
      * pair_macs  = active pairs x |U| (one multiply-add per sample);
      * dfs_visits[l] = depth-l (l = 3, 4) candidate intersections over active

@@ -1,0 +1,271 @@
+// Device building blocks shared by the depth-first kernels: row streaming
+// through scalar registers, the fused and+popcount folds, the bound test, the
+// per-lane best leaf and the depth-4 expansion of one prefix per lane.
+#pragma once
+#include "pdfs_dev.h"
+
+namespace pdfs {
+namespace {
+
+// Read-only view of the round's rows.  The rows do not change while a DFS
+// kernel runs, so reading them through the constant address space lets the
+// compiler fetch a wave-uniform row with scalar loads (one copy per wave,
+// held in SGPRs, used directly as VALU operands).
+typedef const __attribute__((address_space(4))) uint32_t cu32;
+
+// d = (a & b) | c with b a wave-uniform (SGPR) operand.
+__device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+  return d;
+}
+
+// acc + popcount(x)
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+  uint32_t d;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(d) : "v"(x), "v"(acc));
+  return d;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// OR over k of (y[k] & row[k]) with four independent chains.
+template <int W>
+__device__ __forceinline__ uint32_t fold_nonempty(const uint32_t (&y)[W], cu32* row) {
+  uint32_t r[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) r[k] = row[k];
+  uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+  for (int k = 0; k < W; k += 4) {
+    a0 = and_or(y[k], r[k], a0);
+    if (k + 1 < W) a1 = and_or(y[k + 1], r[k + 1], a1);
+    if (k + 2 < W) a2 = and_or(y[k + 2], r[k + 2], a2);
+    if (k + 3 < W) a3 = and_or(y[k + 3], r[k + 3], a3);
+  }
+  return a0 | a1 | a2 | a3;
+}
+
+// sum over k of popcount(y[k] & row[k]), four accumulator chains.
+template <int W>
+__device__ __forceinline__ int popc_and(const uint32_t (&y)[W], cu32* row) {
+  uint32_t r[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) r[k] = row[k];
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+#pragma unroll
+  for (int k = 0; k < W; k += 4) {
+    c0 = bcnt_acc(y[k] & r[k], c0);
+    if (k + 1 < W) c1 = bcnt_acc(y[k + 1] & r[k + 1], c1);
+    if (k + 2 < W) c2 = bcnt_acc(y[k + 2] & r[k + 2], c2);
+    if (k + 3 < W) c3 = bcnt_acc(y[k + 3] & r[k + 3], c3);
+  }
+  return (int)(c0 + c1 + c2 + c3);
+}
+
+__device__ __forceinline__ int popc_and_n(const uint32_t (&z)[kMaxWN32], cu32* row) {
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxWN32; ++k) c += __popc(z[k] & row[k]);
+  return c;
+}
+
+// sum over k of popcount(y[k] & r[k]) for a row already in (scalar) registers
+template <int W>
+__device__ __forceinline__ int popc_and_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+#pragma unroll
+  for (int k = 0; k < W; k += 4) {
+    c0 = bcnt_acc(y[k] & r[k], c0);
+    if (k + 1 < W) c1 = bcnt_acc(y[k + 1] & r[k + 1], c1);
+    if (k + 2 < W) c2 = bcnt_acc(y[k + 2] & r[k + 2], c2);
+    if (k + 3 < W) c3 = bcnt_acc(y[k + 3] & r[k + 3], c3);
+  }
+  return (int)(c0 + c1 + c2 + c3);
+}
+
+// Rows d .. d+KR-1 (clamped to `last`) into scalar registers.
+template <int W, int KR>
+__device__ __forceinline__ void load_rows(uint32_t (&r)[KR][W], cu32* base, int d, int last) {
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    const int dj = d + j < last ? d + j : last;
+#pragma unroll
+    for (int k = 0; k < W; ++k) r[j][k] = base[(size_t)dj * W + k];
+  }
+}
+
+// Makes `next` (the next row index) depend on the rows of the current group.
+// Scalar loads may complete out of order, so waiting for one waits for every
+// load in flight; tying the next group's addresses to the current group's
+// data places that wait before the next loads are issued, which then overlap
+// the current group's arithmetic.
+template <int W, int KR>
+__device__ __forceinline__ void after_arrival(int& next, const uint32_t (&r)[KR][W]) {
+  asm volatile("; rows arrived %1" : "+s"(next) : "s"(r[KR - 1][W - 1]));
+}
+
+__device__ __forceinline__ unsigned long long load_incumbent(RoundState* st) {
+  return __hip_atomic_load(&st->incumbent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// true when a prefix with first indices (a, b) and score bound ub cannot
+// produce the round's answer.
+__device__ __forceinline__ bool dominated(int ub, int a, int b, unsigned long long inc) {
+  if (inc == 0) return false;
+  const int s = (int)(inc >> 32) - 1;
+  if (ub != s) return ub < s;
+  const int g1 = 0xffff - (int)((inc >> 16) & 0xffff);
+  const int g2 = 0xffff - (int)(inc & 0xffff);
+  return a > g1 || (a == g1 && b > g2);
+}
+
+__device__ __forceinline__ unsigned long long leaf_key(int s, int a, int b) {
+  return ((unsigned long long)(s + 1) << 32) | ((unsigned long long)(0xffff - a) << 16) |
+         (unsigned long long)(0xffff - b);
+}
+
+// Orders this wave's LDS writes before its later LDS reads of other lanes'
+// entries.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct Best {
+  int s, tp, fp;
+  int i0, i1, i2, i3;
+  __device__ void init() { s = -1; tp = fp = 0; i0 = i1 = i2 = i3 = 0; }
+  __device__ bool beaten_by(int s2, int j0, int j1, int j2, int j3) const {
+    if (s2 != s) return s2 > s;
+    if (j0 != i0) return j0 < i0;
+    if (j1 != i1) return j1 < i1;
+    if (j2 != i2) return j2 < i2;
+    return j3 < i3;
+  }
+  __device__ void offer(int s2, int tp2, int fp2, int j0, int j1, int j2, int j3) {
+    if (beaten_by(s2, j0, j1, j2, j3)) { s = s2; tp = tp2; fp = fp2; i0 = j0; i1 = j1; i2 = j2; i3 = j3; }
+  }
+};
+
+struct Tally {
+  unsigned long long ne3, ne4, vis3, vis4, bp2, bp3;
+  unsigned long long xv3, xv4, xfp;   // active-candidate visits, FP-counted leaves
+  __device__ void init() { ne3 = ne4 = vis3 = vis4 = bp2 = bp3 = xv3 = xv4 = xfp = 0; }
+};
+
+// Depth-4 expansion of one prefix per lane: y3 (tumour) and z3 (normal)
+// given, c = the lane's depth-3 index, c_first <= every valid lane's c.  The
+// wave streams the candidates d > c_first through scalar loads; each lane
+// masks the d at or below its own c.
+template <int W>
+__device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundState* st,
+                                        const uint32_t (&y3)[W],
+                                        const uint32_t (&z3)[kMaxWN32], uint32_t znz,
+                                        bool valid, int a3, int b3, int c, int c_first,
+                                        Best& best, Tally& tl, unsigned long long& inc) {
+  const int nA = uniform(st->nA);
+  cu32* TA = (cu32*)w.TA;
+  cu32* NA = (cu32*)w.NA;
+  bool live = valid;
+  if (P.mode == kPruneBound) {
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) cnt += __popc(y3[k]);
+    inc = load_incumbent(st);
+    const bool drop = live && dominated(P.p * cnt + P.q * P.n_normal, a3, b3, inc);
+    tl.bp3 += __popcll(__ballot(drop));
+    live = live && !drop;
+    if (!__any(live)) return;
+  }
+  const bool zlive = live && znz != 0;
+  if (live) tl.xv4 += (unsigned long long)(nA - 1 - c);
+  auto step = [&](int d, const uint32_t (&row)[W]) {
+    const int tp = popc_and_r<W>(y3, row);
+    const bool hit = live && d > c && tp > 0;
+    const unsigned long long m = __ballot(hit);
+    if (m == 0) return;
+    tl.ne4 += __popcll(m);
+    int fp = 0;
+    if (__any(hit && zlive)) {
+      if (hit && zlive) {
+        fp = popc_and_n(z3, NA + (size_t)d * kMaxWN32);
+        tl.xfp++;
+      }
+    }
+    if (hit) {
+      const int sc = P.p * tp + P.q * (P.n_normal - fp);
+      best.offer(sc, tp, fp, a3, b3, c, d);
+      if (P.mode == kPruneBound) {
+        const unsigned long long key = leaf_key(sc, a3, b3);
+        if (key > inc) {
+          const unsigned long long old = atomicMax(&st->incumbent, key);
+          inc = old > key ? old : key;
+        }
+      }
+    }
+  };
+  // candidates d stream through two register buffers of KR rows each: the
+  // next group is in flight while the current one is tested
+  constexpr int KR = W <= 16 ? 2 : 1;
+  int d = c_first + 1;
+  if (d < nA) {
+    uint32_t ra[KR][W], rb[KR][W];
+    load_rows<W, KR>(ra, TA, d, nA - 1);
+    for (;;) {
+      int dn = d + KR;
+      after_arrival<W, KR>(dn, ra);
+      load_rows<W, KR>(rb, TA, dn, nA - 1);
+#pragma unroll
+      for (int j = 0; j < KR; ++j)
+        if (d + j < nA) step(d + j, ra[j]);
+      d += KR;
+      if (d >= nA) break;
+      dn = d + KR;
+      after_arrival<W, KR>(dn, rb);
+      load_rows<W, KR>(ra, TA, dn, nA - 1);
+#pragma unroll
+      for (int j = 0; j < KR; ++j)
+        if (d + j < nA) step(d + j, rb[j]);
+      d += KR;
+      if (d >= nA) break;
+    }
+  }
+}
+
+// ---- listing of long-stream depth-3 prefixes (two-phase depth 4)
+constexpr int kStage = 256;   // listed prefixes staged per wave before one global append
+
+__device__ __forceinline__ unsigned long long triple_entry(int a, int b, int c) {
+  return (unsigned long long)a | ((unsigned long long)b << 16) | ((unsigned long long)c << 32);
+}
+
+// Appends q[0, n) to the round's list (one atomic per call) and adds the
+// per-c counts, one atomic per run of equal c among 64 consecutive entries.
+__device__ __forceinline__ void append_staged(const Work& w, RoundState* st,
+                                              const unsigned long long* q, int n, int lane) {
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(&st->n_tri, (unsigned long long)n);
+  base = __shfl(base, 0, 64);
+  for (int i0 = 0; i0 < n; i0 += kWave) {
+    const int i = i0 + lane;
+    const bool v = i < n && base + i < w.tri_cap;
+    const unsigned long long e = v ? q[i] : 0ull;
+    if (v) w.tri[base + i] = e;
+    const int c = v ? (int)(e >> 32) : -1;
+    const int cprev = __shfl_up(c, 1, 64);
+    const bool head = v && (lane == 0 || c != cprev);
+    const unsigned long long H = __ballot(head);
+    // valid lanes form a prefix; counted with the whole wave active
+    const int nvalid = __popcll(__ballot(v));
+    if (head) {
+      const unsigned long long above = H & ~((2ull << lane) - 1ull);
+      const int next = above ? __builtin_ctzll(above) : nvalid;
+      atomicAdd(&w.c_hist[c], (uint32_t)(next - lane));
+    }
+  }
+}
+
+}  // namespace
+}  // namespace pdfs

@@ -29,6 +29,7 @@
 // indices); a prefix is dropped when its bound is below that score, or equal
 // to it with first two indices lexicographically above the key's -- then
 // every tuple under it loses to a tuple already found.
+#include "dfs_core.h"
 #include "pdfs_dev.h"
 #include "slot_reduce.h"
 
@@ -36,163 +37,13 @@ namespace pdfs {
 
 namespace {
 
-
-// Read-only view of the round's rows.  The rows do not change while a DFS
-// kernel runs, so reading them through the constant address space lets the
-// compiler fetch a wave-uniform row with scalar loads (one copy per wave,
-// held in SGPRs, used directly as VALU operands).
-typedef const __attribute__((address_space(4))) uint32_t cu32;
-
-// d = (a & b) | c with b a wave-uniform (SGPR) operand.
-__device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t d;
-  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
-  return d;
-}
-
-// acc + popcount(x)
-__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
-  uint32_t d;
-  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(d) : "v"(x), "v"(acc));
-  return d;
-}
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// OR over k of (y[k] & row[k]) with four independent chains.
-template <int W>
-__device__ __forceinline__ uint32_t fold_nonempty(const uint32_t (&y)[W], cu32* row) {
-  uint32_t r[W];
-#pragma unroll
-  for (int k = 0; k < W; ++k) r[k] = row[k];
-  uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll
-  for (int k = 0; k < W; k += 4) {
-    a0 = and_or(y[k], r[k], a0);
-    if (k + 1 < W) a1 = and_or(y[k + 1], r[k + 1], a1);
-    if (k + 2 < W) a2 = and_or(y[k + 2], r[k + 2], a2);
-    if (k + 3 < W) a3 = and_or(y[k + 3], r[k + 3], a3);
-  }
-  return a0 | a1 | a2 | a3;
-}
-
-// sum over k of popcount(y[k] & row[k]), four accumulator chains.
-template <int W>
-__device__ __forceinline__ int popc_and(const uint32_t (&y)[W], cu32* row) {
-  uint32_t r[W];
-#pragma unroll
-  for (int k = 0; k < W; ++k) r[k] = row[k];
-  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-#pragma unroll
-  for (int k = 0; k < W; k += 4) {
-    c0 = bcnt_acc(y[k] & r[k], c0);
-    if (k + 1 < W) c1 = bcnt_acc(y[k + 1] & r[k + 1], c1);
-    if (k + 2 < W) c2 = bcnt_acc(y[k + 2] & r[k + 2], c2);
-    if (k + 3 < W) c3 = bcnt_acc(y[k + 3] & r[k + 3], c3);
-  }
-  return (int)(c0 + c1 + c2 + c3);
-}
-
-__device__ __forceinline__ int popc_and_n(const uint32_t (&z)[kMaxWN32], cu32* row) {
-  int c = 0;
-#pragma unroll
-  for (int k = 0; k < kMaxWN32; ++k) c += __popc(z[k] & row[k]);
-  return c;
-}
-
-// sum over k of popcount(y[k] & r[k]) for a row already in (scalar) registers
-template <int W>
-__device__ __forceinline__ int popc_and_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
-  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-#pragma unroll
-  for (int k = 0; k < W; k += 4) {
-    c0 = bcnt_acc(y[k] & r[k], c0);
-    if (k + 1 < W) c1 = bcnt_acc(y[k + 1] & r[k + 1], c1);
-    if (k + 2 < W) c2 = bcnt_acc(y[k + 2] & r[k + 2], c2);
-    if (k + 3 < W) c3 = bcnt_acc(y[k + 3] & r[k + 3], c3);
-  }
-  return (int)(c0 + c1 + c2 + c3);
-}
-
-// Rows d .. d+KR-1 (clamped to `last`) into scalar registers.
-template <int W, int KR>
-__device__ __forceinline__ void load_rows(uint32_t (&r)[KR][W], cu32* base, int d, int last) {
-#pragma unroll
-  for (int j = 0; j < KR; ++j) {
-    const int dj = d + j < last ? d + j : last;
-#pragma unroll
-    for (int k = 0; k < W; ++k) r[j][k] = base[(size_t)dj * W + k];
-  }
-}
-
-// Makes `next` (the next row index) depend on the rows of the current group.
-// Scalar loads may complete out of order, so waiting for one waits for every
-// load in flight; tying the next group's addresses to the current group's
-// data places that wait before the next loads are issued, which then overlap
-// the current group's arithmetic.
-template <int W, int KR>
-__device__ __forceinline__ void after_arrival(int& next, const uint32_t (&r)[KR][W]) {
-  asm volatile("; rows arrived %1" : "+s"(next) : "s"(r[KR - 1][W - 1]));
-}
-
-__device__ __forceinline__ unsigned long long load_incumbent(RoundState* st) {
-  return __hip_atomic_load(&st->incumbent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// true when a prefix with first indices (a, b) and score bound ub cannot
-// produce the round's answer.
-__device__ __forceinline__ bool dominated(int ub, int a, int b, unsigned long long inc) {
-  if (inc == 0) return false;
-  const int s = (int)(inc >> 32) - 1;
-  if (ub != s) return ub < s;
-  const int g1 = 0xffff - (int)((inc >> 16) & 0xffff);
-  const int g2 = 0xffff - (int)(inc & 0xffff);
-  return a > g1 || (a == g1 && b > g2);
-}
-
-__device__ __forceinline__ unsigned long long leaf_key(int s, int a, int b) {
-  return ((unsigned long long)(s + 1) << 32) | ((unsigned long long)(0xffff - a) << 16) |
-         (unsigned long long)(0xffff - b);
-}
-
-// Orders this wave's LDS writes before its later LDS reads of other lanes'
-// entries.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-struct Best {
-  int s, tp, fp;
-  int i0, i1, i2, i3;
-  __device__ void init() { s = -1; tp = fp = 0; i0 = i1 = i2 = i3 = 0; }
-  __device__ bool beaten_by(int s2, int j0, int j1, int j2, int j3) const {
-    if (s2 != s) return s2 > s;
-    if (j0 != i0) return j0 < i0;
-    if (j1 != i1) return j1 < i1;
-    if (j2 != i2) return j2 < i2;
-    return j3 < i3;
-  }
-  __device__ void offer(int s2, int tp2, int fp2, int j0, int j1, int j2, int j3) {
-    if (beaten_by(s2, j0, j1, j2, j3)) { s = s2; tp = tp2; fp = fp2; i0 = j0; i1 = j1; i2 = j2; i3 = j3; }
-  }
-};
-
-struct Tally {
-  unsigned long long ne3, ne4, vis3, vis4, bp2, bp3;
-  unsigned long long xv3, xv4, xfp;   // active-candidate visits, FP-counted leaves
-  __device__ void init() { ne3 = ne4 = vis3 = vis4 = bp2 = bp3 = xv3 = xv4 = xfp = 0; }
-};
-
 // Depth-4 pass over n <= 64 staged prefixes (queue entries lane | c << 6,
-// ascending c).
+// ascending c): prefix s's y2 and z2 come from lane s by cross-lane reads.
 template <int W>
 __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundState* st,
                                        const uint32_t* q, int n, const uint32_t (&y2)[W],
                                        const uint32_t (&z2)[kMaxWN32], int a, int b, Best& best,
                                        Tally& tl, unsigned long long& inc, int lane) {
-  const int nA = uniform(st->nA);
   const bool valid = lane < n;
   const uint32_t e = q[valid ? lane : 0];
   const int s = e & 63;
@@ -218,81 +69,22 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
   const int a3 = __shfl(a, s, 64);
   const int b3 = __shfl(b, s, 64);
   const int c_first = uniform((int)(q[0] >> 6));
-  bool live = valid;
-  if (P.mode == kPruneBound) {
-    int cnt = 0;
-#pragma unroll
-    for (int k = 0; k < W; ++k) cnt += __popc(y3[k]);
-    inc = load_incumbent(st);
-    const bool drop = live && dominated(P.p * cnt + P.q * P.n_normal, a3, b3, inc);
-    tl.bp3 += __popcll(__ballot(drop));
-    live = live && !drop;
-    if (!__any(live)) return;
-  }
-  const bool zlive = live && znz != 0;
-  if (live) tl.xv4 += (unsigned long long)(nA - 1 - c);
-  auto step = [&](int d, const uint32_t (&row)[W]) {
-    const int tp = popc_and_r<W>(y3, row);
-    const bool hit = live && d > c && tp > 0;
-    const unsigned long long m = __ballot(hit);
-    if (m == 0) return;
-    tl.ne4 += __popcll(m);
-    int fp = 0;
-    if (__any(hit && zlive)) {
-      if (hit && zlive) {
-        fp = popc_and_n(z3, NA + (size_t)d * kMaxWN32);
-        tl.xfp++;
-      }
-    }
-    if (hit) {
-      const int sc = P.p * tp + P.q * (P.n_normal - fp);
-      best.offer(sc, tp, fp, a3, b3, c, d);
-      if (P.mode == kPruneBound) {
-        const unsigned long long key = leaf_key(sc, a3, b3);
-        if (key > inc) {
-          const unsigned long long old = atomicMax(&st->incumbent, key);
-          inc = old > key ? old : key;
-        }
-      }
-    }
-  };
-  // candidates d stream through two register buffers of KR rows each: the
-  // next group is in flight while the current one is tested
-  constexpr int KR = W <= 16 ? 2 : 1;
-  int d = c_first + 1;
-  if (d < nA) {
-    uint32_t ra[KR][W], rb[KR][W];
-    load_rows<W, KR>(ra, TA, d, nA - 1);
-    for (;;) {
-      int dn = d + KR;
-      after_arrival<W, KR>(dn, ra);
-      load_rows<W, KR>(rb, TA, dn, nA - 1);
-#pragma unroll
-      for (int j = 0; j < KR; ++j)
-        if (d + j < nA) step(d + j, ra[j]);
-      d += KR;
-      if (d >= nA) break;
-      dn = d + KR;
-      after_arrival<W, KR>(dn, rb);
-      load_rows<W, KR>(ra, TA, dn, nA - 1);
-#pragma unroll
-      for (int j = 0; j < KR; ++j)
-        if (d + j < nA) step(d + j, rb[j]);
-      d += KR;
-      if (d >= nA) break;
-    }
-  }
+  expand4<W>(P, w, st, y3, z3, znz, valid, a3, b3, c, c_first, best, tl, inc);
 }
 
 template <int H, int W64>
 __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
   __shared__ uint32_t qbuf[kBlock / kWave][2 * kWave];
+  // h = 4, two-phase: staged long-stream prefixes before a global append
+  __shared__ unsigned long long sbuf[kBlock / kWave][H == 4 ? kStage + kWave : 1];
   RoundState* st = w.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   uint32_t* q = qbuf[wib];
+  unsigned long long* sq = sbuf[wib];
+  int sn = 0;
   // phase 1 expands the seed list, phase 2 the (filtered) work list
   const unsigned long long* __restrict__ plist = phase == 1 ? w.seed_pairs : w.work_pairs;
   const unsigned long long npairs =
@@ -305,6 +97,11 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
       (const __attribute__((address_space(4))) Item*)w.items;
   cu32* TA = (cu32*)w.TA;
   cu32* NA = (cu32*)w.NA;
+  // Two-phase depth 4 (empty-prefix pruning, list allocated): prefixes whose
+  // candidate stream d > c is long are listed for the sorted tile kernel;
+  // the short ones are expanded here.
+  const bool list_long = H == 4 && P.mode == kPruneEmpty && w.tri_cap > 0;
+  const int c_long = nA_all - kLongStream;   // c < c_long: at least kLongStream candidates
 
   Best best;
   best.init();
@@ -415,6 +212,22 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
         // visited at depth 4 for each extended triple: sorted indices in
         // (idx(c), G-1]
         tl.vis4 += (unsigned long long)__popcll(m) * (unsigned long long)(P.G - 1 - uniform(w.act[c]));
+        if (list_long && c < c_long) {
+          const int sp = sn + __popcll(m & ((1ull << lane) - 1));
+          if (hit) sq[sp] = triple_entry(a, b, c);
+          sn += __popcll(m);
+          wave_lds_sync();
+          if (sn >= kStage) {
+            append_staged(w, st, sq, kStage, lane);
+            const int rest = sn - kStage;
+            const unsigned long long moved = (lane < rest) ? sq[kStage + lane] : 0ull;
+            wave_lds_sync();
+            if (lane < rest) sq[lane] = moved;
+            wave_lds_sync();
+            sn = rest;
+          }
+          continue;
+        }
         const int pos = qn + __popcll(m & ((1ull << lane) - 1));
         if (hit) q[pos] = (uint32_t)lane | ((uint32_t)c << 6);
         qn += __popcll(m);
@@ -435,6 +248,7 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
       qn = 0;
     }
   }
+  if (H == 4 && sn > 0) append_staged(w, st, sq, sn, lane);
 
   // block argmax -> slot
   Slot sl = empty_slot();

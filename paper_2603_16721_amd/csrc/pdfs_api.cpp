@@ -56,7 +56,8 @@ hipError_t dalloc(pdfs_ctx* c, T** p, size_t n) {
 void release(pdfs_ctx* c) {
   void* ptrs[] = {c->Ts, c->Ns, c->perm, c->U, c->cols, c->act, c->flags, c->TA, c->NA,
                   c->A8, c->N8, c->pairs, c->work_pairs, c->seed_pairs, c->hist,
-                  c->items, c->slots, c->tallies, c->st, c->recs};
+                  c->items, c->slots, c->tallies, c->st, c->recs, c->tri, c->tri_s,
+                  c->c_hist};
   for (void* p : ptrs) dfree(c, p);
   if (c->h_st && c->own_h_st) (void)hipHostFree(c->h_st);
   for (auto& row : c->ev)
@@ -104,6 +105,8 @@ Work make_work(pdfs_ctx* c, int w64, int target) {
   w.pair_cap = c->pair_cap; w.item_cap = c->item_cap;
   w.w64 = w64; w.wn32 = 2 * c->wn; w.target = target;
   w.chunk = c->chunk_items; w.seed_n = c->seed_pairs_n;
+  w.tri = c->tri; w.tri_s = c->tri_s; w.c_hist = c->c_hist;
+  w.tri_cap = c->two_phase ? c->tri_cap : 0;
   return w;
 }
 
@@ -147,14 +150,29 @@ int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, int slot) {
         CK(c, launch_make_items(P, w, false, s));
         if (tk) CK(c, hipEventRecord(ev[2], s));
       }
-      CK(c, launch_dfs(P, w, 2, s));
+      if (c->two_phase) {
+        // the main DFS lists the prefixes with long depth-4 streams; they are
+        // bucketed by c and expanded in tiles
+        CK(c, launch_tri_begin(w, s));
+        CK(c, launch_dfs(P, w, 2, s));
+        CK(c, launch_sort_triples(w, s));
+        if (tk) CK(c, hipEventRecord(ev[4], s));
+        CK(c, launch_dfs4_tiles(P, w, s));
+      } else {
+        CK(c, launch_dfs(P, w, 2, s));
+      }
       if (tk) CK(c, hipEventRecord(ev[3], s));
     }
   }
-  // slot phases written this round: 0 = h<=2 kernels, 1 = seed DFS, 2 = main DFS
-  const int phases = h <= 2 ? 1 : (c->prune_mode == PDFS_PRUNE_BOUND ? 6 : 4);
-  // counter rows: 0 = pair table (h >= 2), 1 = seed DFS, 2 = main DFS
-  const int tallies = h == 1 ? 0 : (h == 2 ? 1 : (c->prune_mode == PDFS_PRUNE_BOUND ? 7 : 5));
+  // slot phases written this round: 0 = h<=2 kernels, 1 = seed DFS or depth-4
+  // tiles, 2 = main DFS
+  const int phases =
+      h <= 2 ? 1 : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 6 : 4);
+  // counter rows: 0 = pair table (h >= 2), 1 = seed DFS or depth-4 tiles,
+  // 2 = main DFS
+  const int tallies = h == 1 ? 0
+                      : (h == 2 ? 1
+                                : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 7 : 5));
   CK(c, launch_finish_round(P, w, phases, tallies, s));
   return PDFS_OK;
 }
@@ -171,7 +189,7 @@ static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int 
   const Run& r = c->run;
   if (c->use_graphs && !c->time_kernels) {
     const auto key = std::make_tuple(P.h, w.w64, r.p, r.q, r.target, c->prune_mode,
-                                     c->chunk_items, c->seed_pairs_n);
+                                     c->chunk_items, c->seed_pairs_n, c->two_phase);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
       hipGraph_t g = nullptr;
@@ -200,9 +218,60 @@ static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int 
   return PDFS_OK;
 }
 
+// Two-phase depth-4 path (h = 4, empty-prefix pruning): counts the non-empty
+// depth-3 prefixes with long depth-4 streams in the run's first round (U as
+// set for the run) with a depth-3 pass that writes nothing else, and grows
+// the prefix lists to hold them.  Every later round of the run lists a
+// subset.  When the lists would not fit comfortably in free device memory the
+// run uses the single-kernel DFS alone.
+static int32_t size_triples(pdfs_ctx* c, int h, int n_unc) {
+  c->two_phase = false;
+  if (h != 4 || c->prune_mode != PDFS_PRUNE_EMPTY) return PDFS_OK;
+  const int w64 = dfs_row_words(words(n_unc > 0 ? n_unc : 1));
+  if (w64 < 0 || w64 > c->w64_max) return PDFS_OK;   // reported when the run starts
+  if (!c->c_hist) CK(c, dalloc(c, &c->c_hist, (size_t)c->nA_max + 1));
+  const Problem P = make_problem(c, 4, 1, 1);
+  Work w = make_work(c, w64, c->n_tumor + 1);
+  w.tri_cap = 0;
+  hipStream_t s = c->stream;
+  CK(c, launch_run_begin(P, w, 1, s));
+  CK(c, launch_round_begin(P, w, s));
+  CK(c, launch_active(P, w, s));
+  CK(c, launch_gather_active(P, w, true, false, s));
+  CK(c, launch_pairs(P, w, s));
+  CK(c, launch_use_all_pairs(w, s));
+  CK(c, launch_make_items(P, w, false, s));
+  CK(c, launch_tri_begin(w, s));
+  CK(c, launch_count_long(P, w, s));
+  CK(c, hipMemcpyAsync(c->h_st, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
+  CK(c, hipStreamSynchronize(s));
+  if (c->h_st->overflow) return PDFS_OK;   // the run itself reports it
+  const unsigned long long need = c->h_st->n_tri;
+  if (need > c->tri_cap) {
+    const unsigned long long cap = need + need / 16 + 1024;
+    size_t free_b = 0, total_b = 0;
+    CK(c, hipMemGetInfo(&free_b, &total_b));
+    if (cap >= (1ull << 32) || 2 * cap * sizeof(unsigned long long) > free_b / 2) return PDFS_OK;
+    dfree(c, c->tri);
+    dfree(c, c->tri_s);
+    c->tri = c->tri_s = nullptr;
+    c->tri_cap = 0;
+    // captured rounds hold the old list addresses
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    CK(c, dalloc(c, &c->tri, (size_t)cap));
+    CK(c, dalloc(c, &c->tri_s, (size_t)cap));
+    c->tri_cap = cap;
+  }
+  c->two_phase = true;
+  return PDFS_OK;
+}
+
 int32_t run_start(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int max_rounds,
                   int n_unc) {
   int32_t rc = ensure_workspace(c, h);
+  if (rc != PDFS_OK) return rc;
+  rc = size_triples(c, h, n_unc);
   if (rc != PDFS_OK) return rc;
   Run& r = c->run;
   r = Run();
@@ -263,12 +332,17 @@ int32_t run_poll(pdfs_ctx* c, bool wait, bool* ready, bool* done) {
         c->kernel_ns[1] += (int64_t)(ms * 1e6);
         c->kernel_launches[1] += 1;
       }
+      if (r.h >= 3 && c->two_phase) {
+        CK(c, hipEventElapsedTime(&ms, c->ev[k][4], c->ev[k][3]));
+        c->kernel_ns[2] += (int64_t)(ms * 1e6);
+        c->kernel_launches[2] += 1;
+      }
     }
   }
   r.executed_before = st.executed;
   if (st.overflow & 2) {
     r.active = false;
-    return fail(c, PDFS_ERR_DEVICE, "corrupt per-wave result slot");
+    return fail(c, PDFS_ERR_DEVICE, "corrupt per-wave result slot or listed prefix");
   }
   if (st.overflow) {
     r.active = false;
@@ -308,8 +382,10 @@ namespace pdfs {
 
 void begin_stats(pdfs_ctx* c, pdfs_stats* st) {
   if (st) memset(st, 0, sizeof(*st));
-  c->kernel_ns[0] = c->kernel_ns[1] = 0;
-  c->kernel_launches[0] = c->kernel_launches[1] = 0;
+  for (int i = 0; i < 3; ++i) {
+    c->kernel_ns[i] = 0;
+    c->kernel_launches[i] = 0;
+  }
 }
 
 void end_stats(pdfs_ctx* c, pdfs_stats* st, std::chrono::steady_clock::time_point t0) {
@@ -328,7 +404,7 @@ void end_stats(pdfs_ctx* c, pdfs_stats* st, std::chrono::steady_clock::time_poin
   st->dfs_visit_words4 = r.tx_vis_words4;
   st->dfs_leaves = r.tx_leaves;
   st->dfs_fp_leaves = r.tx_fp_leaves;
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < 3; ++i) {
     st->kernel_ns[i] = c->kernel_ns[i];
     st->kernel_launches[i] = c->kernel_launches[i];
   }

@@ -43,7 +43,7 @@ void add_stats(pdfs_stats* dst, const pdfs_stats& s) {
     dst->dfs_visits[l] += s.dfs_visits[l];
   }
   dst->rounds += s.rounds;
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < 3; ++i) {
     dst->kernel_ns[i] += s.kernel_ns[i];
     dst->kernel_launches[i] += s.kernel_launches[i];
   }

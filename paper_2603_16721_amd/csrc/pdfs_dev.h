@@ -37,6 +37,9 @@ constexpr int kSlotPhases = 3;     // pair kernel / seed DFS / main DFS
 constexpr int kSeedPairs = 256;    // bound mode: pairs expanded first to set the incumbent
 constexpr int kSeedCap = 1024;     // seed list capacity (ties at the threshold)
 constexpr int kMaxCount = 1280;    // largest tumour count of a pair (n_tumor limit)
+// two-phase depth 4: depth-3 prefixes with at least this many depth-4
+// candidates left are listed and expanded in sorted tiles
+constexpr int kLongStream = 384;
 
 enum PruneMode { kPruneNone = 0, kPruneEmpty = 1, kPruneBound = 2 };
 
@@ -78,6 +81,9 @@ struct RoundState {
   Counters tot;                    // counters summed over executed rounds
   unsigned long long tx_vis3, tx_vis4, tx_leaves, tx_fp_leaves, tx_pair_macs;
   unsigned long long tx_vis_words3, tx_vis_words4;   // visits x ceil(|U|/64)
+  // ---- two-phase depth-4 (h = 4, empty-prefix pruning)
+  unsigned long long n_tri;        // non-empty depth-3 prefixes listed this round
+  unsigned long long tri_cursor;   // tile cursor of the depth-4 kernel
 };
 
 // Per-block counter rows (summed by the round's finish kernel instead of
@@ -160,6 +166,12 @@ struct Work {
   int32_t target;    // covered-count stop target
   int32_t chunk;     // depth-3 candidates per main-phase DFS item
   int32_t seed_n;    // bound mode: pairs expanded in the seed phase
+  // two-phase depth-4: listed triples a | b << 16 | c << 32, the same sorted
+  // by c, and per-c counts (then bucket offsets), nA entries
+  unsigned long long* tri;
+  unsigned long long* tri_s;
+  uint32_t* c_hist;
+  unsigned long long tri_cap;   // 0: count only
 };
 
 // ---------------------------------------------------------------- launchers
@@ -185,6 +197,13 @@ hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStre
 hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s);
 hipError_t launch_use_all_pairs(const Work& w, hipStream_t s);
 hipError_t launch_dfs(const Problem& P, const Work& w, int phase, hipStream_t s);
+// two-phase depth-4 (h = 4, empty-prefix pruning): the main DFS lists the
+// non-empty depth-3 prefixes with long candidate streams, they are bucketed
+// by c and expanded in tiles of 64
+hipError_t launch_tri_begin(const Work& w, hipStream_t s);
+hipError_t launch_count_long(const Problem& P, const Work& w, hipStream_t s);
+hipError_t launch_sort_triples(const Work& w, hipStream_t s);
+hipError_t launch_dfs4_tiles(const Problem& P, const Work& w, hipStream_t s);
 hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, int tally_mask,
                                hipStream_t s);
 hipError_t launch_clear_slots(Slot* slots, int n, hipStream_t s);

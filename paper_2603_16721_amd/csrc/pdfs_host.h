@@ -61,6 +61,13 @@ struct pdfs_ctx {
   unsigned long long pair_cap = 0;
   pdfs::Item* items = nullptr;
   unsigned long long item_cap = 0;
+  // two-phase depth-4 (h = 4, empty-prefix pruning): triple lists and per-c
+  // counts, sized at run start for the run's first (largest) round
+  unsigned long long* tri = nullptr;
+  unsigned long long* tri_s = nullptr;
+  uint32_t* c_hist = nullptr;
+  unsigned long long tri_cap = 0;
+  bool two_phase = false;              // this run uses the two-phase path
   pdfs::Slot* slots = nullptr;
   unsigned long long* tallies = nullptr;
   pdfs::RoundState* st = nullptr;
@@ -74,14 +81,16 @@ struct pdfs_ctx {
   int chunk_items = 256;               // depth-3 candidates per DFS work item
   int n_cu = 256;                      // compute units of the device
   int seed_pairs_n = 256;              // bound mode: pairs expanded first
-  hipEvent_t ev[pdfs::kMaxChunk][4] = {};
+  hipEvent_t ev[pdfs::kMaxChunk][5] = {};
   hipEvent_t chunk_done = nullptr;
   // per-call accumulation of the timed launches
-  int64_t kernel_ns[2] = {0, 0};
-  int32_t kernel_launches[2] = {0, 0};
+  int64_t kernel_ns[3] = {0, 0, 0};
+  int32_t kernel_launches[3] = {0, 0, 0};
   pdfs::Run run;
-  // captured round graphs keyed by (h, w64, p, q, target, mode, chunk, seed)
-  std::map<std::tuple<int, int, uint32_t, uint32_t, int, int, int, int>, hipGraphExec_t> graphs;
+  // captured round graphs keyed by (h, w64, p, q, target, mode, chunk, seed,
+  // two-phase)
+  std::map<std::tuple<int, int, uint32_t, uint32_t, int, int, int, int, bool>, hipGraphExec_t>
+      graphs;
   size_t bytes = 0;                    // device bytes held (admission accounting)
   bool async_alloc = false;            // stream-ordered allocation (batched / served)
   bool own_h_st = true;                // h_st allocated by the context

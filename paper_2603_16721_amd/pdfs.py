@@ -61,7 +61,7 @@ class pdfs_stats(ctypes.Structure):
                 ("bound_pruned", ctypes.c_uint64 * (MAX_H + 1)),
                 ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("ns_total", ctypes.c_int64),
-                ("kernel_ns", ctypes.c_int64 * 2), ("kernel_launches", ctypes.c_int32 * 2),
+                ("kernel_ns", ctypes.c_int64 * 3), ("kernel_launches", ctypes.c_int32 * 3),
                 ("pair_macs", ctypes.c_uint64), ("dfs_visits", ctypes.c_uint64 * (MAX_H + 1)),
                 ("dfs_leaves", ctypes.c_uint64), ("dfs_fp_leaves", ctypes.c_uint64),
                 ("dfs_visit_words3", ctypes.c_uint64), ("dfs_visit_words4", ctypes.c_uint64)]
