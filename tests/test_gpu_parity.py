@@ -149,6 +149,34 @@ def test_workload_h4_G20000_empty_round1_counters(pdfs):
     _counters_equal(stats, g, 4)
 
 
+def test_two_phase_depth4_medium(pdfs):
+    """h = 4, empty-only walk with more active genes than the long-stream
+    threshold (384 candidates): the round lists long-stream depth-3
+    prefixes for the sorted tile kernel and expands the rest in the main
+    kernel.  Every round and every counter equals the oracle's, plain and
+    with the rounds replayed from captured graphs on a caller stream; a
+    second run on the same context reuses the sized lists."""
+    import torch
+    I = synth.random_tiny(121, 1200, 150, 40, 0.02, 4)
+    T, N = I.packed()
+    exp = cpu.wsc(T, N, I.n_tumor, I.n_normal, 4, 1, 10, max_rounds=3, mode="empty")
+    with pdfs.Solver(T, N, I.n_tumor, I.n_normal, "empty") as s:
+        for _ in range(2):
+            got, stats, _ = s.wsc(4, 1, 10, max_rounds=3)
+            _same_rounds(got, exp.rounds)
+            _counters_equal(stats, exp.counters, 4)
+    st = torch.cuda.Stream()
+    ctx = pdfs.pdfs_create(T, N, I.n_tumor, I.n_normal, "empty", 0, st.cuda_stream,
+                           pdfs.PDFS_OPT_GRAPHS)
+    try:
+        for _ in range(2):
+            got, stats, _ = pdfs.pdfs_wsc_run(ctx, 4, 1, 10, 0, 3, n_tumor=I.n_tumor)
+            _same_rounds(got, exp.rounds)
+            _counters_equal(stats, exp.counters, 4)
+    finally:
+        pdfs.pdfs_destroy(ctx)
+
+
 def test_device_inputs_and_stream(pdfs):
     import torch
     I = synth.random_tiny(55, 80, 190, 70, 0.15, 3)
