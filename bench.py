@@ -190,7 +190,9 @@ def main():
     ap.add_argument("--workload", default="h4_G20000")
     ap.add_argument("--bound-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-every", type=int, default=20)
+    ap.add_argument("--cpu-every", type=int, default=10)
+    ap.add_argument("--no-bound", action="store_true",
+                    help="skip the bound-pruning solve (profiling the empty-mode walk alone)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=400)
@@ -250,26 +252,32 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = scored * args.steps / elapsed
 
-    # dominant kernel: the depth-first kernel (HIP events on the library's stream)
+    # dominant stage: the depth-first kernels of each round (HIP events on the
+    # library's stream around the main DFS kernel, the bucketing kernels and
+    # the depth-4 tile kernel); index 2 = the tile kernel alone
     dfs_ns = sum(s["kernel_ns"][1] for s in stats)
     dfs_launches = sum(s["kernel_launches"][1] for s in stats)
+    tile_ns = sum(s["kernel_ns"][2] for s in stats)
+    tile_launches = sum(s["kernel_launches"][2] for s in stats)
     ops = sum(dfs_alg_ops(s, h, inst.n_normal) for s in stats)
     achieved = ops / (dfs_ns * 1e-9) if dfs_ns else 0.0
     pair_ns = sum(s["kernel_ns"][0] for s in stats)
     pair_ops = 2 * sum(s["pair_macs"] for s in stats)
 
     # ---- exact bound pruning (library default): solve time of the same workload
-    svb = pdfs.Solver(Td, Nd, inst.n_tumor, inst.n_normal, "bound", 0, stream.cuda_stream)
-    rb, _ = solve(svb)
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    for _ in range(args.bound_steps):
-        rb2, _ = solve(svb)
-    torch.cuda.synchronize()
-    bound_ms = 1e3 * (time.perf_counter() - tb) / args.bound_steps
-    svb.close()
-    same = [(r["genes"], r["tp"], r["fp"]) for r in rb2] == \
-        [(r["genes"], r["tp"], r["fp"]) for r in rounds]
+    bound_ms, same = None, None
+    if not args.no_bound:
+        svb = pdfs.Solver(Td, Nd, inst.n_tumor, inst.n_normal, "bound", 0, stream.cuda_stream)
+        rb, _ = solve(svb)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(args.bound_steps):
+            rb2, _ = solve(svb)
+        torch.cuda.synchronize()
+        bound_ms = 1e3 * (time.perf_counter() - tb) / args.bound_steps
+        svb.close()
+        same = [(r["genes"], r["tp"], r["fp"]) for r in rb2] == \
+            [(r["genes"], r["tp"], r["fp"]) for r in rounds]
 
     out = {
         "metric": METRIC,
@@ -292,8 +300,11 @@ def main():
         "bound_matches_empty": same,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
-                     "kernel": "k_dfs<4,*>", "launches": dfs_launches,
+                     "kernel": "depth-first stage per round: k_tri_begin, k_dfs<4,W>, "
+                               "k_scan_c, k_scatter_c, k_dfs4_tiles<W>",
+                     "launches": dfs_launches,
                      "avg_launch_ms": (dfs_ns / max(1, dfs_launches)) * 1e-6,
+                     "tile_kernel_avg_ms": (tile_ns / max(1, tile_launches)) * 1e-6,
                      "ops_per_solve": ops // args.steps},
         "pair_table": {"bound": "mfma", "achieved": pair_ops / max(1e-12, pair_ns * 1e-9) / 1e12,
                        "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "TOP/s (int8)",
