@@ -73,15 +73,13 @@ __device__ __forceinline__ int popc_and_n(const uint32_t (&z)[kMaxWN32], cu32* r
 // sum over k of popcount(y[k] & r[k]) for a row already in (scalar) registers
 template <int W>
 __device__ __forceinline__ int popc_and_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
-  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  uint32_t c0 = 0, c1 = 0;
 #pragma unroll
-  for (int k = 0; k < W; k += 4) {
+  for (int k = 0; k < W; k += 2) {
     c0 = bcnt_acc(y[k] & r[k], c0);
     if (k + 1 < W) c1 = bcnt_acc(y[k + 1] & r[k + 1], c1);
-    if (k + 2 < W) c2 = bcnt_acc(y[k + 2] & r[k + 2], c2);
-    if (k + 3 < W) c3 = bcnt_acc(y[k + 3] & r[k + 3], c3);
   }
-  return (int)(c0 + c1 + c2 + c3);
+  return (int)(c0 + c1);
 }
 
 // Rows d .. d+KR-1 (clamped to `last`) into scalar registers.
@@ -181,11 +179,12 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
   }
   const bool zlive = live && znz != 0;
   if (live) tl.xv4 += (unsigned long long)(nA - 1 - c);
+  const unsigned long long live_m = __ballot(live);
   auto step = [&](int d, const uint32_t (&row)[W]) {
     const int tp = popc_and_r<W>(y3, row);
-    const bool hit = live && d > c && tp > 0;
-    const unsigned long long m = __ballot(hit);
+    const unsigned long long m = __ballot(tp > 0) & __ballot(d > c) & live_m;
     if (m == 0) return;
+    const bool hit = (m >> (threadIdx.x & 63)) & 1ull;
     tl.ne4 += __popcll(m);
     int fp = 0;
     if (__any(hit && zlive)) {
