@@ -32,9 +32,11 @@ __device__ __forceinline__ Slot wave_best(Slot b) {
   return b;
 }
 
+constexpr int kMaxBlockWaves = 16;   // blocks of up to 1024 threads
+
 // Every thread of the block calls this once; thread 0 writes the block's best.
 __device__ __forceinline__ void block_best_to(Slot* dst, Slot b) {
-  __shared__ Slot red[kBlock / kWave];
+  __shared__ Slot red[kMaxBlockWaves];
   b = wave_best(b);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
   __syncthreads();
@@ -50,7 +52,7 @@ __device__ __forceinline__ void block_best_to(Slot* dst, Slot b) {
 // vals: kTallyN values per thread (lanes may hold partial counts).
 __device__ __forceinline__ void block_tally_to(unsigned long long* row,
                                                unsigned long long (&vals)[kTallyN]) {
-  __shared__ unsigned long long red[kBlock / kWave][kTallyN];
+  __shared__ unsigned long long red[kMaxBlockWaves][kTallyN];
   for (int f = 0; f < kTallyN; ++f) {
     unsigned long long v = vals[f];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
