@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -264,6 +265,8 @@ def main():
     pair_ns = sum(s["kernel_ns"][0] for s in stats)
     pair_ops = 2 * sum(s["pair_macs"] for s in stats)
 
+    measured_peak = pdfs.pdfs_measure_int_peak(0)
+
     # ---- exact bound pruning (library default): solve time of the same workload
     bound_ms, same = None, None
     if not args.no_bound:
@@ -298,6 +301,10 @@ def main():
                    "seed": inst.seed},
         "wsc_solve_ms": {"empty": ms_per_step, "bound": bound_ms},
         "bound_matches_empty": same,
+        # the same canonical subsets (the empty-mode leaves) over the bound-mode solve time
+        "bound_effective_subsets_per_s": (scored / (bound_ms * 1e-3)) if bound_ms else None,
+        # Alg. 2's visited depth-h nodes against the C(G,h) subsets of every round
+        "visited_fraction": stats[0]["visited"][h] / (len(rounds) * math.comb(inst.G, h)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
                      "kernel": "depth-first stage per round: k_tri_begin, k_dfs<4,W>, "
@@ -305,7 +312,10 @@ def main():
                      "launches": dfs_launches,
                      "avg_launch_ms": (dfs_ns / max(1, dfs_launches)) * 1e-6,
                      "tile_kernel_avg_ms": (tile_ns / max(1, tile_launches)) * 1e-6,
-                     "ops_per_solve": ops // args.steps},
+                     "ops_per_solve": ops // args.steps,
+                     # the and + popcount pair measured by a probe kernel on this device
+                     "measured_peak": measured_peak / 1e12,
+                     "frac_of_measured": achieved / measured_peak if measured_peak else None},
         "pair_table": {"bound": "mfma", "achieved": pair_ops / max(1e-12, pair_ns * 1e-9) / 1e12,
                        "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "TOP/s (int8)",
                        "frac": pair_ops / max(1e-12, pair_ns * 1e-9) / MFMA_I8_PEAK_OPS,

@@ -192,6 +192,16 @@ int32_t pdfs_wsc_run(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alpha_
 const char *pdfs_strerror(int32_t status);
 const char *pdfs_last_error(const pdfs_ctx *ctx);
 
+/* Measurement support (not part of the method): the integer VALU rate the
+ * device sustains for the depth-first kernels' per-word instruction pair
+ * (an AND with a wave-uniform row word, then a popcount-accumulate), in
+ * lane-operations per second, measured by a short probe kernel on `device`
+ * (a few ms; allocates and frees a small buffer).  The achieved rate of the
+ * depth-first stage is reported against both this and the datasheet peak.
+ * Returns PDFS_OK, PDFS_ERR_INVALID_ARG (NULL output), PDFS_ERR_DEVICE or
+ * PDFS_ERR_OUT_OF_MEMORY. */
+int32_t pdfs_measure_int_peak(int32_t device, double *lane_ops_per_s);
+
 /* ------------------------------------------------------------- batched
  * Many independent cohorts (instances) solved together: each instance keeps
  * its own context, rounds stay device-resident, one round per row width is

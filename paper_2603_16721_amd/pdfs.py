@@ -71,7 +71,7 @@ EXPORTS = ["pdfs_create", "pdfs_destroy", "pdfs_set_prune_mode", "pdfs_best_comb
            "pdfs_wsc_run", "pdfs_strerror", "pdfs_last_error",
            "pdfs_batch_create", "pdfs_batch_run", "pdfs_batch_destroy",
            "pdfs_server_create", "pdfs_server_submit", "pdfs_server_poll", "pdfs_server_drain",
-           "pdfs_server_destroy"]
+           "pdfs_server_destroy", "pdfs_measure_int_peak"]
 PDFS_OPT_GRAPHS = 2
 PDFS_OPT_AUTOTUNE = 4
 
@@ -122,6 +122,8 @@ def _load():
     L.pdfs_server_drain.restype = i32
     L.pdfs_server_destroy.argtypes = [P]
     L.pdfs_server_destroy.restype = None
+    L.pdfs_measure_int_peak.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
+    L.pdfs_measure_int_peak.restype = i32
     return L
 
 
@@ -373,3 +375,12 @@ def pdfs_server_drain(server):
 
 def pdfs_server_destroy(server):
     lib.pdfs_server_destroy(server)
+
+
+def pdfs_measure_int_peak(device=0):
+    """Measured integer VALU rate (lane-ops/s) for the and + popcount pair."""
+    v = ctypes.c_double(0.0)
+    rc = lib.pdfs_measure_int_peak(device, ctypes.byref(v))
+    if rc != PDFS_OK:
+        raise PdfsError(rc, "probe failed")
+    return v.value
