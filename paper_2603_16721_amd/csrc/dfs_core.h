@@ -131,19 +131,23 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A lane's best leaf: score, TP, FP and the tuple of active indices, packed
+// i0 << 48 | i1 << 32 | i2 << 16 | i3 (every index < 65536), so that the
+// order (S desc, tuple asc) is two integer comparisons and the update is
+// plain selects -- no branches in the candidate loops.
 struct Best {
   int s, tp, fp;
-  int i0, i1, i2, i3;
-  __device__ void init() { s = -1; tp = fp = 0; i0 = i1 = i2 = i3 = 0; }
-  __device__ bool beaten_by(int s2, int j0, int j1, int j2, int j3) const {
-    if (s2 != s) return s2 > s;
-    if (j0 != i0) return j0 < i0;
-    if (j1 != i1) return j1 < i1;
-    if (j2 != i2) return j2 < i2;
-    return j3 < i3;
-  }
+  unsigned long long t;
+  __device__ void init() { s = -1; tp = fp = 0; t = ~0ull; }
+  __device__ int idx(int k) const { return (int)((t >> (48 - 16 * k)) & 0xffffull); }
   __device__ void offer(int s2, int tp2, int fp2, int j0, int j1, int j2, int j3) {
-    if (beaten_by(s2, j0, j1, j2, j3)) { s = s2; tp = tp2; fp = fp2; i0 = j0; i1 = j1; i2 = j2; i3 = j3; }
+    const unsigned long long t2 = ((unsigned long long)j0 << 48) | ((unsigned long long)j1 << 32) |
+                                  ((unsigned long long)j2 << 16) | (unsigned long long)j3;
+    const bool take = s2 > s || (s2 == s && t2 < t);
+    s = take ? s2 : s;
+    tp = take ? tp2 : tp;
+    fp = take ? fp2 : fp;
+    t = take ? t2 : t;
   }
 };
 

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs4_tiles(Problem
   Slot sl = empty_slot();
   if (best.s >= 0) {
     sl.s = best.s; sl.tp = best.tp; sl.fp = best.fp;
-    sl.idx[0] = best.i0; sl.idx[1] = best.i1; sl.idx[2] = best.i2; sl.idx[3] = best.i3;
+    sl.idx[0] = best.idx(0); sl.idx[1] = best.idx(1); sl.idx[2] = best.idx(2); sl.idx[3] = best.idx(3);
   }
   block_best_to(&w.slots[(size_t)1 * kSlotsPerPhase + blockIdx.x], sl);
   unsigned long long v[kTallyN] = {0};
