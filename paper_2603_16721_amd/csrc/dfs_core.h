@@ -46,6 +46,18 @@ __device__ __forceinline__ uint32_t fold_nonempty(const uint32_t (&y)[W], cu32* 
   return a0 | a1 | a2 | a3;
 }
 
+// OR over k of (y[k] & r[k]) for a row already in (scalar) registers.
+template <int W>
+__device__ __forceinline__ uint32_t fold_nonempty_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
+  uint32_t a0 = 0, a1 = 0;
+#pragma unroll
+  for (int k = 0; k < W; k += 2) {
+    a0 = and_or(y[k], r[k], a0);
+    if (k + 1 < W) a1 = and_or(y[k + 1], r[k + 1], a1);
+  }
+  return a0 | a1;
+}
+
 // sum over k of popcount(y[k] & row[k]), four accumulator chains.
 template <int W>
 __device__ __forceinline__ int popc_and(const uint32_t (&y)[W], cu32* row) {

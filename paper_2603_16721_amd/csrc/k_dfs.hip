@@ -75,9 +75,14 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
 template <int H, int W64>
 __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
-  __shared__ uint32_t qbuf[kBlock / kWave][2 * kWave];
+  // Narrow rows (<= 8 words): KG consecutive candidate rows arrive with one
+  // 16-dword scalar load and are tested as a group; their prefixes are queued
+  // before any depth-4 pass, so the queues hold up to KG more waves' worth.
+  constexpr bool kNarrow = W <= 8;
+  constexpr int KG = kNarrow ? 16 / W : 1;
+  __shared__ uint32_t qbuf[kBlock / kWave][kWave * (KG + 1)];
   // h = 4, two-phase: staged long-stream prefixes before a global append
-  __shared__ unsigned long long sbuf[kBlock / kWave][H == 4 ? kStage + kWave : 1];
+  __shared__ unsigned long long sbuf[kBlock / kWave][H == 4 ? kStage + KG * kWave : 1];
   RoundState* st = w.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63;
@@ -170,12 +175,11 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
     }
 
     int qn = 0;
-    for (int c = c_lo; c < c_hi; ++c) {
+    // Non-empty depth-3 prefixes (lane, c) of candidate c, m = their lanes:
+    // scored (h = 3), or bound-tested and then listed or queued (h = 4).
+    auto on_hits = [&](int c, unsigned long long m) {
+      bool hit = (m >> lane) & 1ull;
       cu32* row = TA + (size_t)c * W;
-      const uint32_t acc = fold_nonempty<W>(y2, row);
-      bool hit = valid && c > b && acc != 0;
-      unsigned long long m = __ballot(hit);
-      if (m == 0) continue;
       tl.ne3 += __popcll(m);
       if (H == 3) {
         int fp = 0;
@@ -197,50 +201,101 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
             }
           }
         }
-      } else {
-        if (P.mode == kPruneBound) {
-          bool drop = false;
-          if (hit) {
-            const int cnt = popc_and<W>(y2, row);
-            drop = dominated(P.p * cnt + P.q * P.n_normal, a, b, inc);
-          }
-          tl.bp3 += __popcll(__ballot(drop));
-          hit = hit && !drop;
-          m = __ballot(hit);
-          if (m == 0) continue;
+        return;
+      }
+      if (P.mode == kPruneBound) {
+        bool drop = false;
+        if (hit) {
+          const int cnt = popc_and<W>(y2, row);
+          drop = dominated(P.p * cnt + P.q * P.n_normal, a, b, inc);
         }
-        // visited at depth 4 for each extended triple: sorted indices in
-        // (idx(c), G-1]
-        tl.vis4 += (unsigned long long)__popcll(m) * (unsigned long long)(P.G - 1 - uniform(w.act[c]));
-        if (list_long && c < c_long) {
-          const int sp = sn + __popcll(m & ((1ull << lane) - 1));
-          if (hit) sq[sp] = triple_entry(a, b, c);
-          sn += __popcll(m);
-          wave_lds_sync();
-          if (sn >= kStage) {
-            append_staged(w, st, sq, kStage, lane);
-            const int rest = sn - kStage;
-            const unsigned long long moved = (lane < rest) ? sq[kStage + lane] : 0ull;
-            wave_lds_sync();
-            if (lane < rest) sq[lane] = moved;
-            wave_lds_sync();
-            sn = rest;
-          }
-          continue;
-        }
-        const int pos = qn + __popcll(m & ((1ull << lane) - 1));
-        if (hit) q[pos] = (uint32_t)lane | ((uint32_t)c << 6);
-        qn += __popcll(m);
+        tl.bp3 += __popcll(__ballot(drop));
+        hit = hit && !drop;
+        m = __ballot(hit);
+        if (m == 0) return;
+      }
+      // visited at depth 4 for each extended triple: sorted indices in
+      // (idx(c), G-1]
+      tl.vis4 += (unsigned long long)__popcll(m) * (unsigned long long)(P.G - 1 - uniform(w.act[c]));
+      if (list_long && c < c_long) {
+        const int sp = sn + __popcll(m & ((1ull << lane) - 1));
+        if (hit) sq[sp] = triple_entry(a, b, c);
+        sn += __popcll(m);
         wave_lds_sync();
-        if (qn >= kWave) {
-          depth4<W>(P, w, st, q, kWave, y2, z2, a, b, best, tl, inc, lane);
-          const int rest = qn - kWave;
-          const uint32_t moved = (lane < rest) ? q[kWave + lane] : 0u;
-          wave_lds_sync();
-          if (lane < rest) q[lane] = moved;
-          wave_lds_sync();
-          qn = rest;
+        return;
+      }
+      const int pos = qn + __popcll(m & ((1ull << lane) - 1));
+      if (hit) q[pos] = (uint32_t)lane | ((uint32_t)c << 6);
+      qn += __popcll(m);
+      wave_lds_sync();
+    };
+    // Staged long-stream prefixes go out once kStage are waiting; every full
+    // wave of queued prefixes becomes a depth-4 pass.
+    auto drain = [&]() {
+      if (H != 4) return;
+      if (sn >= kStage) {
+        append_staged(w, st, sq, sn, lane);
+        sn = 0;
+      }
+      int off = 0;
+      while (qn - off >= kWave) {
+        depth4<W>(P, w, st, q + off, kWave, y2, z2, a, b, best, tl, inc, lane);
+        off += kWave;
+      }
+      if (off > 0) {
+        const int rest = qn - off;   // < kWave
+        const uint32_t moved = (lane < rest) ? q[off + lane] : 0u;
+        wave_lds_sync();
+        if (lane < rest) q[lane] = moved;
+        wave_lds_sync();
+        qn = rest;
+      }
+    };
+    if (!kNarrow) {
+      for (int c = c_lo; c < c_hi; ++c) {
+        const uint32_t acc = fold_nonempty<W>(y2, TA + (size_t)c * W);
+        const unsigned long long m = __ballot(valid && c > b && acc != 0);
+        if (m == 0) continue;
+        on_hits(c, m);
+        drain();
+      }
+    } else {
+      // KG rows per group (one 16-dword scalar load), the next group in
+      // flight while the current one is tested; rows past c_hi are loaded
+      // (inside the round's row allocation) but never tested
+      const unsigned long long valid_m = __ballot(valid);
+      auto group = [&](int c0, const uint32_t (&rows)[KG][W]) {
+        unsigned long long m[KG];
+        unsigned long long any = 0;
+#pragma unroll
+        for (int j = 0; j < KG; ++j) {
+          const uint32_t acc = fold_nonempty_r<W>(y2, rows[j]);
+          m[j] = c0 + j < c_hi ? __ballot(acc != 0) & __ballot(c0 + j > b) & valid_m : 0ull;
+          any |= m[j];
         }
+        if (any == 0) return;
+#pragma unroll
+        for (int j = 0; j < KG; ++j)
+          if (m[j]) on_hits(c0 + j, m[j]);
+        drain();
+      };
+      constexpr int kNoClamp = 0x7fffffff;
+      uint32_t rA[KG][W], rB[KG][W];
+      int c0 = c_lo;
+      load_rows<W, KG>(rA, TA, c0, kNoClamp);
+      for (;;) {
+        int cn = c0 + KG;
+        after_arrival<W, KG>(cn, rA);
+        load_rows<W, KG>(rB, TA, cn, kNoClamp);
+        group(c0, rA);
+        c0 += KG;
+        if (c0 >= c_hi) break;
+        cn = c0 + KG;
+        after_arrival<W, KG>(cn, rB);
+        load_rows<W, KG>(rA, TA, cn, kNoClamp);
+        group(c0, rB);
+        c0 += KG;
+        if (c0 >= c_hi) break;
       }
     }
     if (H == 4 && qn > 0) {
