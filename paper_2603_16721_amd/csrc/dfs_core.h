@@ -85,6 +85,12 @@ __device__ __forceinline__ int popc_and_n(const uint32_t (&z)[kMaxWN32], cu32* r
 // sum over k of popcount(y[k] & r[k]) for a row already in (scalar) registers
 template <int W>
 __device__ __forceinline__ int popc_and_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
+  if (W <= 4) {   // one chain: no final add
+    uint32_t c0 = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) c0 = bcnt_acc(y[k] & r[k], c0);
+    return (int)c0;
+  }
   uint32_t c0 = 0, c1 = 0;
 #pragma unroll
   for (int k = 0; k < W; k += 2) {
@@ -112,6 +118,21 @@ __device__ __forceinline__ void load_rows(uint32_t (&r)[KR][W], cu32* base, int 
 // the current group's arithmetic.
 template <int W, int KR>
 __device__ __forceinline__ void after_arrival(int& next, const uint32_t (&r)[KR][W]) {
+  asm volatile("; rows arrived %1" : "+s"(next) : "s"(r[KR - 1][W - 1]));
+}
+
+// KR consecutive rows starting at p into scalar registers (no clamping).
+template <int W, int KR>
+__device__ __forceinline__ void load_group(uint32_t (&r)[KR][W], cu32* p) {
+#pragma unroll
+  for (int j = 0; j < KR; ++j)
+#pragma unroll
+    for (int k = 0; k < W; ++k) r[j][k] = p[j * W + k];
+}
+
+// after_arrival for a row pointer.
+template <int W, int KR>
+__device__ __forceinline__ void group_arrived(cu32*& next, const uint32_t (&r)[KR][W]) {
   asm volatile("; rows arrived %1" : "+s"(next) : "s"(r[KR - 1][W - 1]));
 }
 
@@ -169,10 +190,34 @@ struct Tally {
   __device__ void init() { ne3 = ne4 = vis3 = vis4 = bp2 = bp3 = xv3 = xv4 = xfp = 0; }
 };
 
+// Largest v over the wave.
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return uniform(v);
+}
+
+// Smallest TP with which a leaf can still replace a best leaf of score s.  A
+// leaf scores at most p*TP + q*N_n (no false positives); it replaces the best
+// if it scores more, or the same with a smaller tuple.  tie_wins says whether
+// the leaves in question can have the smaller tuple.  Always >= 1, so it also
+// implies a non-empty leaf.
+__device__ __forceinline__ int min_tp_for(const Problem& P, int s, bool tie_wins) {
+  const int e = s - P.q * P.n_normal;   // p*TP must reach e (tie) or pass it
+  if (e < 0) return 1;
+  const uint32_t p = (uint32_t)P.p;
+  if (p == 0) return tie_wins && e == 0 ? 1 : 0x7fffffff;   // TP does not count
+  const uint32_t t = tie_wins ? ((uint32_t)e + p - 1u) / p : (uint32_t)e / p + 1u;
+  return t > 1u ? (int)t : 1;
+}
+
 // Depth-4 expansion of one prefix per lane: y3 (tumour) and z3 (normal)
 // given, c = the lane's depth-3 index, c_first <= every valid lane's c.  The
 // wave streams the candidates d > c_first through scalar loads; each lane
-// masks the d at or below its own c.
+// masks the d at or below its own c.  Every non-empty leaf is counted; only
+// those whose TP reaches the lane's threshold (min_tp_for of the lane's best)
+// are scored and offered, which leaves the answer unchanged: a leaf below it
+// cannot replace the leaf the lane already holds.
 template <int W>
 __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundState* st,
                                         const uint32_t (&y3)[W],
@@ -195,13 +240,20 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
   }
   const bool zlive = live && znz != 0;
   if (live) tl.xv4 += (unsigned long long)(nA - 1 - c);
-  const unsigned long long live_m = __ballot(live);
-  auto step = [&](int d, const uint32_t (&row)[W]) {
-    const int tp = popc_and_r<W>(y3, row);
-    const unsigned long long m = __ballot(tp > 0) & __ballot(d > c) & live_m;
-    if (m == 0) return;
+  // a dead lane's TP is 0 at every d: it never counts nor offers
+  uint32_t y[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) y[k] = live ? y3[k] : 0u;
+  const int cmax = wave_max(live ? c : -1);   // d > cmax: no lane masks d
+  // the prefix's leaves all have a smaller tuple than the best exactly when
+  // (a3, b3, c) precedes the best's first three indices
+  const unsigned long long pre = ((unsigned long long)a3 << 32) | ((unsigned long long)b3 << 16) |
+                                 (unsigned long long)c;
+  int thr = min_tp_for(P, best.s, pre < (best.t >> 16));
+  uint32_t ne = 0;   // non-empty leaves of this pass (< 64 * nA)
+  // leaves of candidate d in lanes m (TP >= thr): score and offer
+  auto offer = [&](int d, int tp, unsigned long long m) {
     const bool hit = (m >> (threadIdx.x & 63)) & 1ull;
-    tl.ne4 += __popcll(m);
     int fp = 0;
     if (__any(hit && zlive)) {
       if (hit && zlive) {
@@ -212,6 +264,8 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
     if (hit) {
       const int sc = P.p * tp + P.q * (P.n_normal - fp);
       best.offer(sc, tp, fp, a3, b3, c, d);
+      // a best from this prefix has a smaller tuple than its later leaves
+      thr = min_tp_for(P, best.s, pre < (best.t >> 16));
       if (P.mode == kPruneBound) {
         const unsigned long long key = leaf_key(sc, a3, b3);
         if (key > inc) {
@@ -221,32 +275,63 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
       }
     }
   };
-  // candidates d stream through two register buffers of KR rows each: the
-  // next group is in flight while the current one is tested
-  constexpr int KR = W <= 16 ? 2 : 1;
   int d = c_first + 1;
-  if (d < nA) {
-    uint32_t ra[KR][W], rb[KR][W];
-    load_rows<W, KR>(ra, TA, d, nA - 1);
-    for (;;) {
-      int dn = d + KR;
-      after_arrival<W, KR>(dn, ra);
-      load_rows<W, KR>(rb, TA, dn, nA - 1);
+  // d <= cmax: lanes with c >= d mask it
+  for (; d <= cmax && d < nA; ++d) {
+    uint32_t row[W];
 #pragma unroll
-      for (int j = 0; j < KR; ++j)
-        if (d + j < nA) step(d + j, ra[j]);
-      d += KR;
-      if (d >= nA) break;
-      dn = d + KR;
-      after_arrival<W, KR>(dn, rb);
-      load_rows<W, KR>(ra, TA, dn, nA - 1);
-#pragma unroll
-      for (int j = 0; j < KR; ++j)
-        if (d + j < nA) step(d + j, rb[j]);
-      d += KR;
-      if (d >= nA) break;
-    }
+    for (int k = 0; k < W; ++k) row[k] = TA[(size_t)d * W + k];
+    const int tp = popc_and_r<W>(y, row);
+    const unsigned long long dm = __ballot(d > c);
+    ne += (uint32_t)__popcll(__ballot(tp > 0) & dm);
+    const unsigned long long m = __ballot(tp >= thr) & dm;
+    if (m) offer(d, tp, m);
   }
+  if (d >= nA) {
+    tl.ne4 += ne;
+    return;
+  }
+  // d > cmax: every lane tests every d.  Candidates stream through two
+  // register buffers of KR rows each, the next group in flight while the
+  // current one is tested.  TA holds at least 128 rows past the last active
+  // one (whole 128-row tiles plus 128), so groups are read unclamped; rows
+  // at or past nA are zeroed before use (TP 0: neither counted nor offered).
+  constexpr int KR = W <= 4 ? 4 : (W <= 16 ? 2 : 1);
+  auto step = [&](int dd, const uint32_t (&row)[W]) {
+    const int tp = popc_and_r<W>(y, row);
+    ne += (uint32_t)__popcll(__ballot(tp > 0));
+    const unsigned long long m = __ballot(tp >= thr);
+    if (m) offer(dd, tp, m);
+  };
+  auto group = [&](uint32_t (&r)[KR][W]) {
+    if (d + KR > nA) {
+#pragma unroll
+      for (int j = 1; j < KR; ++j)
+#pragma unroll
+        for (int k = 0; k < W; ++k) r[j][k] = d + j < nA ? r[j][k] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < KR; ++j) step(d + j, r[j]);
+    d += KR;
+  };
+  cu32* ptr = TA + (size_t)d * W;
+  uint32_t ra[KR][W], rb[KR][W];
+  load_group<W, KR>(ra, ptr);
+  for (;;) {
+    cu32* pn = ptr + KR * W;
+    group_arrived<W, KR>(pn, ra);
+    load_group<W, KR>(rb, pn);
+    group(ra);
+    if (d >= nA) break;
+    ptr = pn;
+    pn = ptr + KR * W;
+    group_arrived<W, KR>(pn, rb);
+    load_group<W, KR>(ra, pn);
+    group(rb);
+    if (d >= nA) break;
+    ptr = pn;
+  }
+  tl.ne4 += ne;
 }
 
 // ---- listing of long-stream depth-3 prefixes (two-phase depth 4)

@@ -58,6 +58,8 @@ TINY = [
     (111, 300, 90, 30, 0.05, 2, (1, 10)),
     (112, 45, 150, 40, 0.2, 1, (1, 10)),
     (113, 4, 100, 10, 0.8, 4, (1, 10)),
+    (114, 60, 100, 40, 0.2, 4, (0, 1)),
+    (115, 80, 150, 60, 0.15, 4, (7, 2)),
 ]
 
 
