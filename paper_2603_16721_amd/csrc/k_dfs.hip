@@ -68,12 +68,14 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
   }
   const int a3 = __shfl(a, s, 64);
   const int b3 = __shfl(b, s, 64);
+  // visited at depth 4 below the prefix: sorted indices in (idx(c), G-1]
+  if (valid) tl.vis4 += (unsigned long long)(P.G - 1 - w.act[c]);
   const int c_first = uniform((int)(q[0] >> 6));
   expand4<W>(P, w, st, y3, z3, znz, valid, a3, b3, c, c_first, best, tl, inc);
 }
 
 template <int H, int W64>
-__global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
+__global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
   // Narrow rows (<= 8 words): KG consecutive candidate rows arrive with one
   // 16-dword scalar load and are tested as a group; their prefixes are queued
@@ -137,6 +139,7 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
     if (it >= nitems) break;
     const int c_lo = uniform((int)items[it].c_lo);
     const int c_hi = uniform((int)items[it].c_hi);
+    if (c_lo >= c_hi) continue;   // never made by the item builder
     const uint32_t batch = (uint32_t)uniform((int)items[it].batch);
     const uint32_t first_chunk = (uint32_t)uniform((int)items[it].pad) & 1u;
     const unsigned long long pi = (unsigned long long)batch * kPairBatch + lane;
@@ -214,9 +217,6 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
         m = __ballot(hit);
         if (m == 0) return;
       }
-      // visited at depth 4 for each extended triple: sorted indices in
-      // (idx(c), G-1]
-      tl.vis4 += (unsigned long long)__popcll(m) * (unsigned long long)(P.G - 1 - uniform(w.act[c]));
       if (list_long && c < c_long) {
         const int sp = sn + __popcll(m & ((1ull << lane) - 1));
         if (hit) sq[sp] = triple_entry(a, b, c);
@@ -317,12 +317,12 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs(Problem P, Wor
   if (lane == 0) {
     v[kTNe3] = tl.ne3;
     v[kTNe4] = H == 4 ? tl.ne4 : 0;
-    v[kTVis4] = H == 4 ? tl.vis4 : 0;
     v[kTBp2] = tl.bp2;
     v[kTBp3] = tl.bp3;
     v[kTLeaves] = H == 3 ? tl.ne3 : tl.ne4;
   }
   v[kTVis3] = tl.vis3;
+  v[kTVis4] = H == 4 ? tl.vis4 : 0;
   v[kTXv3] = tl.xv3;
   v[kTXv4] = tl.xv4;
   v[kTXfp] = tl.xfp;

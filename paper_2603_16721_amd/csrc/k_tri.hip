@@ -231,6 +231,8 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs4_tiles(Problem
               NA[(size_t)c * kMaxWN32 + k] & vmask;
       znz |= z3[k];
     }
+    // visited at depth 4 below the prefix: sorted indices in (idx(c), G-1]
+    if (valid) tl.vis4 += (unsigned long long)(P.G - 1 - w.act[c]);
     int cmin = valid ? c : 0x7fffffff;
     for (int o = 32; o > 0; o >>= 1) cmin = min(cmin, __shfl_xor(cmin, o, 64));
     expand4<W>(P, w, st, y3, z3, znz, valid, a3, b3, c, uniform(cmin), best, tl, inc);
@@ -247,6 +249,7 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs4_tiles(Problem
     v[kTNe4] = tl.ne4;
     v[kTLeaves] = tl.ne4;
   }
+  v[kTVis4] = tl.vis4;
   v[kTXv4] = tl.xv4;
   v[kTXfp] = tl.xfp;
   block_tally_to(w.tallies + ((size_t)1 * kPersistBlocks + blockIdx.x) * kTallyN, v);
