@@ -196,6 +196,8 @@ def main():
                     help="skip the bound-pruning solve (profiling the empty-mode walk alone)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-exhaustive", action="store_true",
+                    help="skip the pruned-vs-exhaustive first-round comparison")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-speed", type=float, default=1.0,
                     help="arrival-rate multiplier of the 20 req/s stream")
@@ -267,6 +269,35 @@ def main():
 
     measured_peak = pdfs.pdfs_measure_int_peak(0)
 
+    # ---- pruned vs exhaustive walk, first greedy round of the two smaller
+    # workloads (the exhaustive walk of h4_G20000 visits ~6.7e15 leaves a round)
+    exhaustive = None
+    if not args.no_exhaustive:
+        exhaustive = {}
+        for name in ("h2_G500", "h3_G5000"):
+            wi = synth.WORKLOADS[name]()
+            Ti, Ni = wi.packed()
+            row = {}
+            for mode in ("none", "empty"):
+                svx = pdfs.Solver(Ti, Ni, wi.n_tumor, wi.n_normal, mode, 0, stream.cuda_stream)
+                r1, st1, _ = svx.wsc(wi.h, wi.alpha_p, wi.alpha_q, max_rounds=1)
+                torch.cuda.synchronize()
+                tx = time.perf_counter()
+                r1, st1, _ = svx.wsc(wi.h, wi.alpha_p, wi.alpha_q, max_rounds=1)
+                torch.cuda.synchronize()
+                row[mode] = {"round1_ms": 1e3 * (time.perf_counter() - tx),
+                             "visited": st1["visited"][1:wi.h + 1],
+                             "nonempty": st1["nonempty"][1:wi.h + 1],
+                             "genes": r1[0]["genes"] if r1 else None}
+                svx.close()
+            row["same_answer"] = row["none"]["genes"] == row["empty"]["genes"]
+            row["visited_fraction"] = row["empty"]["visited"][-1] / math.comb(wi.G, wi.h)
+            row["pruning_speedup"] = row["none"]["round1_ms"] / row["empty"]["round1_ms"]
+            exhaustive[name] = row
+            print(f"[bench] exhaustive vs pruned round 1, {name}: "
+                  f"{row['none']['round1_ms']:.2f} ms vs {row['empty']['round1_ms']:.2f} ms",
+                  file=sys.stderr, flush=True)
+
     # ---- exact bound pruning (library default): solve time of the same workload
     bound_ms, same = None, None
     if not args.no_bound:
@@ -322,6 +353,8 @@ def main():
                        "avg_launch_ms": pair_ns / max(1, sum(s["kernel_launches"][0]
                                                              for s in stats)) * 1e-6},
     }
+    if exhaustive is not None:
+        out["exhaustive_vs_pruned_round1"] = exhaustive
     if not args.no_batched:
         print("[bench] batched: 32 instances, plain serial vs batched", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(pdfs, data_b)

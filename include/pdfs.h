@@ -63,8 +63,12 @@ extern "C" {
  *   covering c uncovered tumour samples can reach at most p*c + q*N_n, so it
  *   is not extended when that cannot beat the best combination found so far.
  *   Exact: it returns the same combinations as EMPTY.  The default.
- * PDFS_PRUNE_NONE: exhaustive enumeration; accepted by the interface but the
- *   GPU path returns PDFS_ERR_UNSUPPORTED for it. */
+ * PDFS_PRUNE_NONE: exhaustive enumeration (the pruning-off baseline the paper
+ *   compares against, Sec. IV): every gene is walked and every prefix is
+ *   extended, empty or not; leaves with TP = 0 are visited but never chosen,
+ *   so the combinations equal EMPTY's and only the visited counters grow
+ *   (to the full loop-bound counts of Alg. 2).  Its first use on a context
+ *   regrows the row-indexed buffers to G rows. */
 #define PDFS_PRUNE_NONE 0
 #define PDFS_PRUNE_EMPTY 1
 #define PDFS_PRUNE_BOUND 2

@@ -99,6 +99,8 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
   const unsigned long long nit = st->n_items;
   const uint32_t nitems = (uint32_t)uniform((int)(nit < w.item_cap ? nit : w.item_cap));
   const int nA_all = uniform(st->nA);
+  // exhaustive mode (h = 4): every depth-3 prefix is extended, empty or not
+  const bool all_pre = H == 4 && P.mode == kPruneNone;
   if (blockIdx.x == 0 && threadIdx.x == 0 && nit > w.item_cap) st->overflow |= 1;
   const __attribute__((address_space(4))) Item* items =
       (const __attribute__((address_space(4))) Item*)w.items;
@@ -180,10 +182,15 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
     int qn = 0;
     // Non-empty depth-3 prefixes (lane, c) of candidate c, m = their lanes:
     // scored (h = 3), or bound-tested and then listed or queued (h = 4).
-    auto on_hits = [&](int c, unsigned long long m) {
+    // mq = the prefixes to extend: m, or every (lane, c) in exhaustive mode
+    auto on_hits = [&](int c, unsigned long long m, unsigned long long mq) {
       bool hit = (m >> lane) & 1ull;
       cu32* row = TA + (size_t)c * W;
       tl.ne3 += __popcll(m);
+      if (all_pre) {
+        hit = (mq >> lane) & 1ull;
+        m = mq;
+      }
       if (H == 3) {
         int fp = 0;
         if (__any(hit && znz != 0)) {
@@ -255,8 +262,9 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
       for (int c = c_lo; c < c_hi; ++c) {
         const uint32_t acc = fold_nonempty<W>(y2, TA + (size_t)c * W);
         const unsigned long long m = __ballot(valid && c > b && acc != 0);
-        if (m == 0) continue;
-        on_hits(c, m);
+        const unsigned long long mq = all_pre ? __ballot(valid && c > b) : m;
+        if (mq == 0) continue;
+        on_hits(c, m, mq);
         drain();
       }
     } else {
@@ -265,18 +273,20 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
       // (inside the round's row allocation) but never tested
       const unsigned long long valid_m = __ballot(valid);
       auto group = [&](int c0, const uint32_t (&rows)[KG][W]) {
-        unsigned long long m[KG];
+        unsigned long long m[KG], mq[KG];
         unsigned long long any = 0;
 #pragma unroll
         for (int j = 0; j < KG; ++j) {
           const uint32_t acc = fold_nonempty_r<W>(y2, rows[j]);
-          m[j] = c0 + j < c_hi ? __ballot(acc != 0) & __ballot(c0 + j > b) & valid_m : 0ull;
-          any |= m[j];
+          const unsigned long long in = c0 + j < c_hi ? __ballot(c0 + j > b) & valid_m : 0ull;
+          m[j] = __ballot(acc != 0) & in;
+          mq[j] = all_pre ? in : m[j];
+          any |= mq[j];
         }
         if (any == 0) return;
 #pragma unroll
         for (int j = 0; j < KG; ++j)
-          if (m[j]) on_hits(c0 + j, m[j]);
+          if (mq[j]) on_hits(c0 + j, m[j], mq[j]);
         drain();
       };
       constexpr int kNoClamp = 0x7fffffff;

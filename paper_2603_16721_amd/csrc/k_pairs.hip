@@ -162,6 +162,8 @@ __global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
           const int i = bi * kBT + wr * 64 + m * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
           const int c = acc[m][n][r];
           const bool ok = jok && i < j && i < amax1 && c > 0;
+          // exhaustive mode extends the empty pairs as well
+          const bool emit = jok && i < j && i < amax1 && (c > 0 || P.mode == kPruneNone);
           if (kH2) {
             if (ok) {
               const int s = P.p * c + P.q * (P.n_normal - accn[m][n][r]);
@@ -169,11 +171,11 @@ __global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
                 bs = s; btp = c; bfp = accn[m][n][r]; bi_ = i; bj_ = j;
               }
             }
-          } else if (ok) {
+          } else if (emit) {
             ++nhit;
             vis3 += (unsigned long long)(bound3 - sj);
           }
-          if (kH2) ne2 += ok ? 1 : 0;
+          ne2 += ok ? 1 : 0;
         }
       }
     }
@@ -193,7 +195,6 @@ __global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
       __syncthreads();
       unsigned long long pos = wbase + (unsigned long long)(incl - nhit);
       for (int q = 0; q < wave; ++q) pos += (unsigned long long)wsum[q];
-      ne2 += (unsigned long long)nhit;
       if (nhit) {
 #pragma unroll
         for (int n = 0; n < 2; ++n) {
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
             for (int r = 0; r < 16; ++r) {
               const int i = bi * kBT + wr * 64 + m * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
               const int c = acc[m][n][r];
-              if (jok && i < j && i < amax1 && c > 0) {
+              if (jok && i < j && i < amax1 && (c > 0 || P.mode == kPruneNone)) {
                 if (pos < w.pair_cap)
                   w.pairs[pos] = (unsigned long long)i | ((unsigned long long)j << 16) |
                                  ((unsigned long long)c << 32);

@@ -124,7 +124,8 @@ __global__ void k_active_flags(Problem P, Work w) {
   uint64_t acc = 0;
   const uint64_t* row = w.Ts + (size_t)g * P.wt;
   for (int k = 0; k < P.wt; ++k) acc |= row[k] & w.U[k];
-  w.flags[g] = acc != 0;
+  // 1: the gene meets U; 2: it does not, but exhaustive mode walks it anyway
+  w.flags[g] = acc != 0 ? 1 : (P.mode == kPruneNone ? 2 : 0);
 }
 
 // One block of 1024 threads: ordered compaction of the active flags, the
@@ -133,12 +134,14 @@ __global__ void k_active_flags(Problem P, Work w) {
 __global__ __launch_bounds__(1024) void k_active_scan(Problem P, Work w) {
   __shared__ int wsum[16];
   __shared__ unsigned long long vsum[16];
+  __shared__ int nsum[16];
   RoundState* st = w.st;
   if (st->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int h = P.h;
   int base = 0;
   unsigned long long vis2 = 0;
+  int ne1 = 0;   // genes meeting U within the depth-1 bound
   for (int g0 = 0; g0 < P.G; g0 += 1024) {
     int g = g0 + tid;
     int f = (g < P.G) ? w.flags[g] : 0;
@@ -154,18 +157,30 @@ __global__ __launch_bounds__(1024) void k_active_scan(Problem P, Work w) {
     if (f) {
       w.act[base + off + pre] = g;
       if (h >= 2 && g <= P.G - h) vis2 += (unsigned long long)(P.G - h + 1 - g);
+      if (f == 1 && g <= P.G - h) ++ne1;
     }
     base += tot;
     __syncthreads();
   }
-  for (int o = 32; o > 0; o >>= 1) vis2 += __shfl_xor(vis2, o, 64);
-  if (lane == 0) vsum[wid] = vis2;
+  for (int o = 32; o > 0; o >>= 1) {
+    vis2 += __shfl_xor(vis2, o, 64);
+    ne1 += __shfl_xor(ne1, o, 64);
+  }
+  if (lane == 0) {
+    vsum[wid] = vis2;
+    nsum[wid] = ne1;
+  }
   __syncthreads();
   if (tid == 0) {
     unsigned long long v = 0;
-    for (int i = 0; i < 16; ++i) v += vsum[i];
+    int n1 = 0;
+    for (int i = 0; i < 16; ++i) {
+      v += vsum[i];
+      n1 += nsum[i];
+    }
     st->nA = base;
     st->cnt.visited[1] = (unsigned long long)(P.G - h + 1);
+    st->cnt.nonempty[1] = (unsigned long long)n1;
     if (h >= 2) st->cnt.visited[2] = v;
   }
   // amax[l] = number of active genes with sorted index <= G-h+l-1.  act is
@@ -178,7 +193,6 @@ __global__ __launch_bounds__(1024) void k_active_scan(Problem P, Work w) {
       if (w.act[mid] <= lim) lo = mid + 1; else hi = mid;
     }
     st->amax[tid] = lo;
-    if (tid == 1) st->cnt.nonempty[1] = (unsigned long long)lo;
   }
 }
 
@@ -243,10 +257,7 @@ __global__ __launch_bounds__(256) void k_h1(Problem P, Work w) {
   Slot sl = empty_slot();
   if (bs >= 0) { sl.s = bs; sl.tp = btp; sl.fp = bfp; sl.idx[0] = bi; }
   block_best_to(&w.slots[blockIdx.x], sl);
-  if (gw == 0 && lane == 0) {
-    w.st->cnt.nonempty[1] = (unsigned long long)nA;
-    w.st->cnt.visited[1] = (unsigned long long)P.G;
-  }
+  if (gw == 0 && lane == 0) w.st->cnt.visited[1] = (unsigned long long)P.G;
 }
 
 __global__ void k_clear_slots(Slot* slots, int n) {

@@ -70,9 +70,40 @@ void release(pdfs_ctx* c) {
 
 int words(int n) { return (n + 63) / 64; }
 
+// Exhaustive mode makes every gene a row of the round (its row over the
+// uncovered samples may be empty), so the row-indexed buffers must hold G rows
+// instead of the first round's active count.  Drops the buffers sized by the
+// old count (they are re-made on demand) and the captured rounds that hold
+// their addresses.
+static int32_t grow_for_all_genes(pdfs_ctx* c) {
+  if (c->nA_max >= c->G) return PDFS_OK;
+  CK(c, hipStreamSynchronize(c->stream));
+  void** bufs[] = {(void**)&c->TA, (void**)&c->NA, (void**)&c->A8, (void**)&c->N8,
+                   (void**)&c->pairs, (void**)&c->work_pairs, (void**)&c->seed_pairs,
+                   (void**)&c->items, (void**)&c->tri, (void**)&c->tri_s, (void**)&c->c_hist};
+  for (void** b : bufs) {
+    dfree(c, *b);
+    *b = nullptr;
+  }
+  c->pair_cap = c->item_cap = c->tri_cap = 0;
+  c->two_phase = false;
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->nA_max = c->G;
+  const size_t rows = (size_t)((c->nA_max + 127) / 128 * 128 + 128);
+  CK(c, dalloc(c, &c->TA, rows * 2 * (size_t)c->w64_max));
+  CK(c, dalloc(c, &c->NA, rows * (size_t)kMaxWN32));
+  CK(c, dalloc(c, &c->A8, rows * (size_t)unpacked_row_bytes(c->w64_max)));
+  return PDFS_OK;
+}
+
 // Allocates the pair list, item list and normal bytes when a call first needs
 // them.
 int32_t ensure_workspace(pdfs_ctx* c, int h) {
+  if (c->prune_mode == PDFS_PRUNE_NONE) {
+    const int32_t rc = grow_for_all_genes(c);
+    if (rc != PDFS_OK) return rc;
+  }
   if (h >= 3 && !c->pairs) {
     unsigned long long n = (unsigned long long)c->nA_max * (c->nA_max > 0 ? c->nA_max - 1 : 0) / 2;
     if (n < 64) n = 64;
@@ -436,8 +467,6 @@ int32_t check_call(pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
   if (p > 65535u || q > 65535u || smax >= 1073741824.0)
     return fail(c, PDFS_ERR_INVALID_ARG, "p*n_tumor + q*n_normal must stay below 2^30");
   if (h > 4) return fail(c, PDFS_ERR_UNSUPPORTED, "GPU path runs h = 1..4");
-  if (c->prune_mode == PDFS_PRUNE_NONE)
-    return fail(c, PDFS_ERR_UNSUPPORTED, "exhaustive mode is not run on the GPU");
   CK(c, hipSetDevice(c->device));
   return PDFS_OK;
 }

@@ -78,6 +78,44 @@ def test_wsc_tiny(pdfs, case, mode):
         _counters_equal(stats, exp.counters, h)
 
 
+# Exhaustive mode: every prefix is extended, empty or not.  The oracle's
+# exhaustive walk of seed 108 (G = 200, h = 4) takes minutes; the rest take
+# seconds.
+TINY_ALL = [c for c in TINY if c[0] != 108]
+
+
+@pytest.mark.parametrize("case", TINY_ALL, ids=[f"s{c[0]}_G{c[1]}_h{c[5]}" for c in TINY_ALL])
+def test_wsc_tiny_exhaustive(pdfs, case):
+    seed, G, nt, nn, d, h, (p, q) = case
+    I = synth.random_tiny(seed, G, nt, nn, d, h, alpha=(p, q))
+    T, N = I.packed()
+    exp = cpu.wsc(T, N, nt, nn, h, p, q, mode="none")
+    with pdfs.Solver(T, N, nt, nn, "none") as s:
+        got, stats, final = s.wsc(h, p, q)
+    _same_rounds(got, exp.rounds)
+    assert np.array_equal(final, exp.final_uncovered)
+    _counters_equal(stats, exp.counters, h)
+
+
+def test_exhaustive_mode_switches(pdfs):
+    # one context: empty-prefix walk, then exhaustive (every gene becomes a row
+    # of the round, buffers regrown), then empty again
+    I = synth.random_tiny(116, 150, 120, 40, 0.08, 4, alpha=(1, 10))
+    T, N = I.packed()
+    with pdfs.Solver(T, N, 120, 40, "empty") as s:
+        for mode in ("empty", "none", "empty", "bound", "none"):
+            s.set_prune_mode(mode)
+            exp = cpu.wsc(T, N, 120, 40, 4, 1, 10, max_rounds=3,
+                          mode="bound" if mode == "bound" else mode)
+            got, stats, _ = s.wsc(4, 1, 10, max_rounds=3)
+            _same_rounds(got, exp.rounds)
+            if mode != "bound":
+                _counters_equal(stats, exp.counters, 4)
+            if mode == "none":
+                # every depth-2 prefix within the loop bounds is extended
+                assert stats["visited"][3] > exp.counters["nonempty"][2]
+
+
 @pytest.mark.parametrize("case", TINY[1:9], ids=[f"s{c[0]}" for c in TINY[1:9]])
 def test_best_combo_random_masks(pdfs, case):
     seed, G, nt, nn, d, h, (p, q) = case
