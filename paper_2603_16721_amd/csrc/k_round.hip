@@ -18,7 +18,7 @@ namespace pdfs {
 
 namespace {
 
-__device__ __forceinline__ bool lex_less4(const int32_t* x, const int32_t* y, int h) {
+__device__ __forceinline__ bool lex_less(const int32_t* x, const int32_t* y, int h) {
   for (int i = 0; i < h; ++i) {
     if (x[i] != y[i]) return x[i] < y[i];
   }
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
                                                       int tally_mask) {
   __shared__ Slot red[16];
   __shared__ int s_found;
-  __shared__ int32_t s_sidx[4];
+  __shared__ int32_t s_sidx[kMaxH];
   __shared__ unsigned long long tsum[16][kTallyN];
   RoundState* st = w.st;
   if (st->done) return;
@@ -320,12 +320,13 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
     __syncthreads();
   }
   Slot b;
-  b.s = -1; b.tp = b.fp = 0; b.idx[0] = b.idx[1] = b.idx[2] = b.idx[3] = 0; b.pad = 0;
+  b.s = -1; b.tp = b.fp = 0; b.pad = 0;
+  for (int i = 0; i < kMaxH; ++i) b.idx[i] = 0;
   for (int ph = 0; ph < kSlotPhases; ++ph) {
     if (!((phase_mask >> ph) & 1)) continue;
     for (int i = tid; i < kSlotsPerPhase; i += 1024) {
       Slot c = w.slots[(size_t)ph * kSlotsPerPhase + i];
-      if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less4(c.idx, b.idx, h))) b = c;
+      if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less(c.idx, b.idx, h))) b = c;
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -333,15 +334,15 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
     c.s = __shfl_xor(b.s, o, 64);
     c.tp = __shfl_xor(b.tp, o, 64);
     c.fp = __shfl_xor(b.fp, o, 64);
-    for (int i = 0; i < 4; ++i) c.idx[i] = __shfl_xor(b.idx[i], o, 64);
-    if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less4(c.idx, b.idx, h))) b = c;
+    for (int i = 0; i < kMaxH; ++i) c.idx[i] = __shfl_xor(b.idx[i], o, 64);
+    if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less(c.idx, b.idx, h))) b = c;
   }
   if (lane == 0) red[wid] = b;
   __syncthreads();
   if (tid == 0) {
     for (int i = 1; i < 16; ++i) {
       Slot c = red[i];
-      if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less4(c.idx, b.idx, h))) b = c;
+      if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less(c.idx, b.idx, h))) b = c;
     }
     RoundRecord r;
     r.h = h;

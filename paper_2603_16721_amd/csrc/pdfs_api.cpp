@@ -165,7 +165,18 @@ int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, int slot) {
     if (tk) CK(c, hipEventRecord(ev[0], s));
     CK(c, launch_pairs(P, w, s));
     if (tk) CK(c, hipEventRecord(ev[1], s));
-    if (h >= 3) {
+    if (h >= 5) {
+      // depths 3..h walked per lane (no seed phase: bound pruning is not
+      // applied below depth 2 here, the answers are the same), over the
+      // unfiltered pair list
+      Work wd = w;
+      wd.work_pairs = wd.pairs;
+      CK(c, launch_use_all_pairs(wd, s));
+      CK(c, launch_make_items(P, wd, false, s));
+      if (tk) CK(c, hipEventRecord(ev[2], s));
+      CK(c, launch_dfs_deep(P, wd, s));
+      if (tk) CK(c, hipEventRecord(ev[3], s));
+    } else if (h >= 3) {
       if (c->prune_mode == PDFS_PRUNE_BOUND) {
         // seed phase: expand the highest-count pairs first so that the
         // incumbent is close to the round's answer, then keep only the pairs
@@ -197,13 +208,15 @@ int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, int slot) {
   }
   // slot phases written this round: 0 = h<=2 kernels, 1 = seed DFS or depth-4
   // tiles, 2 = main DFS
-  const int phases =
-      h <= 2 ? 1 : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 6 : 4);
+  const int phases = h <= 2 ? 1
+                     : (h >= 5 ? 4 : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 6 : 4));
   // counter rows: 0 = pair table (h >= 2), 1 = seed DFS or depth-4 tiles,
   // 2 = main DFS
+  // (h >= 5: the deep walk adds its counters directly)
   const int tallies = h == 1 ? 0
-                      : (h == 2 ? 1
-                                : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 7 : 5));
+                      : (h == 2 || h >= 5
+                             ? 1
+                             : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 7 : 5));
   CK(c, launch_finish_round(P, w, phases, tallies, s));
   return PDFS_OK;
 }
@@ -466,7 +479,6 @@ int32_t check_call(pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
   double smax = (double)p * c->n_tumor + (double)q * c->n_normal;
   if (p > 65535u || q > 65535u || smax >= 1073741824.0)
     return fail(c, PDFS_ERR_INVALID_ARG, "p*n_tumor + q*n_normal must stay below 2^30");
-  if (h > 4) return fail(c, PDFS_ERR_UNSUPPORTED, "GPU path runs h = 1..4");
   CK(c, hipSetDevice(c->device));
   return PDFS_OK;
 }

@@ -114,9 +114,9 @@ struct RoundRecord {
 };
 
 struct Slot {
-  int32_t s;        // score, -1 = empty
+  int32_t s;             // score, -1 = empty
   int32_t tp, fp;
-  int32_t idx[4];   // active-list indices, ascending
+  int32_t idx[kMaxH];    // active-list indices, ascending (zero past h)
   int32_t pad;
 };
 
@@ -197,6 +197,8 @@ hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStre
 hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s);
 hipError_t launch_use_all_pairs(const Work& w, hipStream_t s);
 hipError_t launch_dfs(const Problem& P, const Work& w, int phase, hipStream_t s);
+// h = 5..8: per-lane subtree walk with an index stack (main phase only)
+hipError_t launch_dfs_deep(const Problem& P, const Work& w, hipStream_t s);
 // two-phase depth-4 (h = 4, empty-prefix pruning): the main DFS lists the
 // non-empty depth-3 prefixes with long candidate streams, they are bucketed
 // by c and expanded in tiles of 64

@@ -8,14 +8,15 @@ namespace pdfs {
 __device__ __forceinline__ bool slot_better(const Slot& c, const Slot& b) {
   if (c.s != b.s) return c.s > b.s;
   if (c.s < 0) return false;
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kMaxH; ++i)
     if (c.idx[i] != b.idx[i]) return c.idx[i] < b.idx[i];
   return false;
 }
 
 __device__ __forceinline__ Slot empty_slot() {
   Slot e;
-  e.s = -1; e.tp = e.fp = 0; e.idx[0] = e.idx[1] = e.idx[2] = e.idx[3] = 0; e.pad = 0;
+  e.s = -1; e.tp = e.fp = 0; e.pad = 0;
+  for (int i = 0; i < kMaxH; ++i) e.idx[i] = 0;
   return e;
 }
 
@@ -25,7 +26,7 @@ __device__ __forceinline__ Slot wave_best(Slot b) {
     c.s = __shfl_xor(b.s, o, 64);
     c.tp = __shfl_xor(b.tp, o, 64);
     c.fp = __shfl_xor(b.fp, o, 64);
-    for (int i = 0; i < 4; ++i) c.idx[i] = __shfl_xor(b.idx[i], o, 64);
+    for (int i = 0; i < kMaxH; ++i) c.idx[i] = __shfl_xor(b.idx[i], o, 64);
     c.pad = 0;
     if (slot_better(c, b)) b = c;
   }

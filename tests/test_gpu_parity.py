@@ -78,6 +78,33 @@ def test_wsc_tiny(pdfs, case, mode):
         _counters_equal(stats, exp.counters, h)
 
 
+# h = 5..8: the per-lane subtree walk (every mode; BOUND runs the same walk)
+DEEP = [
+    # seed, G, n_tumor, n_normal, density, h, alpha
+    (201, 40, 100, 30, 0.25, 5, (1, 10)),
+    (202, 30, 150, 50, 0.35, 6, (1, 10)),
+    (203, 24, 80, 20, 0.45, 7, (2, 5)),
+    (204, 20, 64, 64, 0.5, 8, (1, 10)),
+    (205, 60, 200, 40, 0.15, 5, (3, 7)),
+    (206, 36, 130, 0, 0.3, 6, (0, 1)),
+]
+
+
+@pytest.mark.parametrize("case", DEEP, ids=[f"s{c[0]}_G{c[1]}_h{c[5]}" for c in DEEP])
+@pytest.mark.parametrize("mode", ["empty", "none", "bound"])
+def test_wsc_deep(pdfs, case, mode):
+    seed, G, nt, nn, d, h, (p, q) = case
+    I = synth.random_tiny(seed, G, nt, nn, d, h, alpha=(p, q))
+    T, N = I.packed()
+    exp = cpu.wsc(T, N, nt, nn, h, p, q, mode="empty" if mode == "bound" else mode)
+    with pdfs.Solver(T, N, nt, nn, mode) as s:
+        got, stats, final = s.wsc(h, p, q)
+    _same_rounds(got, exp.rounds)
+    assert np.array_equal(final, exp.final_uncovered)
+    if mode != "bound":
+        _counters_equal(stats, exp.counters, h)
+
+
 # Exhaustive mode: every prefix is extended, empty or not.  The oracle's
 # exhaustive walk of seed 108 (G = 200, h = 4) takes minutes; the rest take
 # seconds.
@@ -258,10 +285,6 @@ def test_edge_cases(pdfs):
     for h in (1, 2, 3, 4, 6):
         exp = cpu.wsc(T, N, 80, 20, h, 1, 10, mode="empty")
         with pdfs.Solver(T, N, 80, 20, "bound") as s:
-            if h > 4:
-                with pytest.raises(pdfs.PdfsError):
-                    s.wsc(h)
-                continue
             got, _, _ = s.wsc(h)
         _same_rounds(got, exp.rounds)
     # no normals at all
