@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-exhaustive", action="store_true",
                     help="skip the pruned-vs-exhaustive first-round comparison")
+    ap.add_argument("--no-heldout", action="store_true",
+                    help="skip the 75/25 held-out coverage report")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-speed", type=float, default=1.0,
                     help="arrival-rate multiplier of the 20 req/s stream")
@@ -298,6 +300,21 @@ def main():
                   f"{row['none']['round1_ms']:.2f} ms vs {row['empty']['round1_ms']:.2f} ms",
                   file=sys.stderr, flush=True)
 
+    # ---- held-out coverage (accuracy protocol): learn on a 75 % split of the
+    # samples with the GPU path, score the frozen combinations on both splits
+    held = None
+    if not args.no_heldout:
+        from paper_2603_16721_amd import heldout
+        held = {}
+        for name in ("h3_G5000", "h4_G20000"):
+            wi = inst if name == args.workload else synth.WORKLOADS[name]()
+            r = heldout.learn_and_evaluate(pdfs, wi, 0.25, seed=16721600)
+            r.pop("combos")
+            held[name] = r
+            print(f"[bench] held-out {name}: {r['combinations']} combinations, test sensitivity "
+                  f"{r['test']['sensitivity']:.3f}, specificity {r['test']['specificity']:.3f}",
+                  file=sys.stderr, flush=True)
+
     # ---- exact bound pruning (library default): solve time of the same workload
     bound_ms, same = None, None
     if not args.no_bound:
@@ -355,6 +372,8 @@ def main():
     }
     if exhaustive is not None:
         out["exhaustive_vs_pruned_round1"] = exhaustive
+    if held is not None:
+        out["heldout_75_25"] = held
     if not args.no_batched:
         print("[bench] batched: 32 instances, plain serial vs batched", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(pdfs, data_b)
