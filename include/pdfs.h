@@ -147,7 +147,8 @@ typedef struct {
     /* Work the kernels had to do, counted inside them (always filled):
      * pair_macs  = active pairs x |U| (one multiply-add per sample);
      * dfs_visits[l] = depth-l (l = 3, 4) candidate intersections over active
-     *   genes; dfs_leaves = scored leaves; dfs_fp_leaves = leaves whose
+     *   genes; dfs_leaves = non-empty leaves (each compared with its
+     *   lane's best); dfs_fp_leaves = leaves whose
      *   normal intersection had to be counted; dfs_visit_words3/4 = depth-3/4
      *   visits times ceil(|U|/64) of their round, summed (so words / visits
      *   is the mean row length in 64-bit words). */
