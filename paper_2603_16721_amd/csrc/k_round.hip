@@ -273,7 +273,9 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
                                                       int tally_mask) {
   __shared__ Slot red[16];
   __shared__ int s_found;
+  __shared__ Slot s_best;
   __shared__ int32_t s_sidx[kMaxH];
+  __shared__ int32_t s_gene[kMaxH];
   __shared__ unsigned long long tsum[16][kTallyN];
   RoundState* st = w.st;
   if (st->done) return;
@@ -339,60 +341,68 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
   }
   if (lane == 0) red[wid] = b;
   __syncthreads();
+  // The tail is a chain of small global reads and writes; they are spread
+  // over threads (one per chosen gene, one per depth) instead of one thread.
   if (tid == 0) {
     for (int i = 1; i < 16; ++i) {
       Slot c = red[i];
       if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less(c.idx, b.idx, h))) b = c;
     }
-    RoundRecord r;
-    r.h = h;
-    r.found = b.s >= 0;
-    if (r.found) {
+    int ok = b.s >= 0;
+    if (ok) {
       // a slot index outside the active list would mean a corrupt slot
       const int nA = st->nA;
       for (int i = 0; i < h; ++i)
-        if (b.idx[i] < 0 || b.idx[i] >= nA || (i > 0 && b.idx[i] <= b.idx[i - 1])) r.found = 0;
-      if (b.tp <= 0) r.found = 0;
-      if (!r.found) st->overflow |= 2;
+        if (b.idx[i] < 0 || b.idx[i] >= nA || (i > 0 && b.idx[i] <= b.idx[i - 1])) ok = 0;
+      if (b.tp <= 0) ok = 0;
+      if (!ok) st->overflow |= 2;
     }
-    for (int i = 0; i < kMaxH; ++i) { r.sorted_idx[i] = -1; r.genes[i] = -1; }
-    r.tp = r.fp = r.tn = 0;
-    r.uncovered_before = st->n_unc;
-    r.score_num = 0;
-    r.score_den = (int64_t)P.q * (int64_t)(st->n_unc + P.n_normal);
-    if (r.found) {
-      for (int i = 0; i < h; ++i) {
-        int si = w.act[b.idx[i]];
-        r.sorted_idx[i] = si;
-        r.genes[i] = w.perm[si];
-        s_sidx[i] = si;
-      }
-      r.tp = b.tp;
-      r.fp = b.fp;
-      r.tn = P.n_normal - b.fp;
-      r.score_num = (int64_t)P.p * b.tp + (int64_t)P.q * r.tn;
-    }
-    s_found = r.found;
-    st->found = r.found;
-    if (r.found && st->rounds < w.rec_cap) w.recs[st->rounds] = r;
+    s_best = b;
+    s_found = ok;
   }
   __syncthreads();
-  if (s_found && tid < P.wt) {
+  b = s_best;
+  const int found = s_found;
+  if (found && tid < h) {
+    const int si = w.act[b.idx[tid]];
+    s_sidx[tid] = si;
+    s_gene[tid] = w.perm[si];
+  }
+  // whole-run totals per depth (this round's counters are final here)
+  if (tid >= 64 && tid <= 64 + kMaxH) {
+    const int l = tid - 64;
+    st->tot.visited[l] += st->cnt.visited[l];
+    st->tot.nonempty[l] += st->cnt.nonempty[l];
+    st->tot.bound_pruned[l] += st->cnt.bound_pruned[l];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    RoundRecord r;
+    r.h = h;
+    r.found = found;
+    for (int i = 0; i < kMaxH; ++i) {
+      r.sorted_idx[i] = (found && i < h) ? s_sidx[i] : -1;
+      r.genes[i] = (found && i < h) ? s_gene[i] : -1;
+    }
+    r.tp = found ? b.tp : 0;
+    r.fp = found ? b.fp : 0;
+    r.tn = found ? P.n_normal - b.fp : 0;
+    r.uncovered_before = st->n_unc;
+    r.score_num = found ? (int64_t)P.p * b.tp + (int64_t)P.q * r.tn : 0;
+    r.score_den = (int64_t)P.q * (int64_t)(st->n_unc + P.n_normal);
+    st->found = found;
+    if (found && st->rounds < w.rec_cap) w.recs[st->rounds] = r;
+  }
+  if (found && tid < P.wt) {
     uint64_t cov = w.U[tid];
     for (int i = 0; i < h; ++i) cov &= w.Ts[(size_t)s_sidx[i] * P.wt + tid];
     w.U[tid] &= ~cov;
   }
   if (tid == 0) {
-    int cov = (P.n_tumor - st->n_unc) + (s_found ? b.tp : 0);
+    int cov = (P.n_tumor - st->n_unc) + (found ? b.tp : 0);
     st->covered = cov;
-    st->rounds += s_found ? 1 : 0;
+    st->rounds += found ? 1 : 0;
     st->executed += 1;
-    // whole-run totals
-    for (int l = 0; l <= kMaxH; ++l) {
-      st->tot.visited[l] += st->cnt.visited[l];
-      st->tot.nonempty[l] += st->cnt.nonempty[l];
-      st->tot.bound_pruned[l] += st->cnt.bound_pruned[l];
-    }
     const unsigned long long wu = (unsigned long long)((st->n_unc + 63) / 64);
     st->tx_vis3 += st->x_vis3;
     st->tx_vis4 += st->x_vis4;
