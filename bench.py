@@ -31,6 +31,29 @@ METRIC = ("h-hit subsets scored/s + WSC solve time, batched/served vs plain; "
 VALU_PEAK = 256 * 4 * 16 * 2.4e9          # lane-instructions/s (CUs x SIMDs x lanes x clock)
 MFMA_I8_PEAK_OPS = 5.0e15                 # dense int8 MFMA, ops/s (2 per multiply-add)
 
+# HBM traffic of the depth-first stage, per launch (one round), from two
+# rocprofv3 --pmc runs of one h4_G20000 solve (FETCH_SIZE, WRITE_SIZE), each
+# scaled by what the counter reads for a 1 GiB device copy (FETCH_SIZE reads
+# half the bytes, WRITE_SIZE all of them); profiles/dfs_stage_h4_G20000_traffic.md.
+# Valid for the stage kernels' sources it was taken on (hash below); reported
+# as null once they change.
+STAGE_SOURCES = ("k_dfs.hip", "k_tri.hip", "dfs_core.h", "slot_reduce.h", "pdfs_dev.h")
+STAGE_TRAFFIC = {"sources_sha256_16": "1231811aae9cec0b", "workload": "h4_G20000",
+                 "bytes_per_launch": (2.0 * 4165132 + 1.0 * 12961216) * 1024 / 133}
+
+
+def stage_traffic(workload):
+    import hashlib
+    h = hashlib.sha256()
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_16721_amd", "csrc")
+    for f in STAGE_SOURCES:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != STAGE_TRAFFIC["sources_sha256_16"] or \
+            workload != STAGE_TRAFFIC["workload"]:
+        return None
+    return STAGE_TRAFFIC["bytes_per_launch"]
+
 
 def words(n):
     return (n + 63) // 64
@@ -270,6 +293,7 @@ def main():
     pair_ops = 2 * sum(s["pair_macs"] for s in stats)
 
     measured_peak = pdfs.pdfs_measure_int_peak(0)
+    traffic = stage_traffic(inst.name)
 
     # ---- pruned vs exhaustive walk, first greedy round of the two smaller
     # workloads (the exhaustive walk of h4_G20000 visits ~6.7e15 leaves a round)
@@ -354,7 +378,11 @@ def main():
         # Alg. 2's visited depth-h nodes against the C(G,h) subsets of every round
         "visited_fraction": stats[0]["visited"][h] / (len(rounds) * math.comb(inst.G, h)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK,
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "traffic_GBps": (traffic / (dfs_ns / max(1, dfs_launches) * 1e-9) / 1e9
+                                      if traffic and dfs_ns else None),
                      "kernel": "depth-first stage per round: k_tri_begin, k_dfs<4,W>, "
                                "k_scan_c, k_scatter_c, k_dfs4_tiles<W>",
                      "launches": dfs_launches,
