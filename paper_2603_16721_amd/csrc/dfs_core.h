@@ -218,7 +218,7 @@ __device__ __forceinline__ int min_tp_for(const Problem& P, int s, bool tie_wins
 // those whose TP reaches the lane's threshold (min_tp_for of the lane's best)
 // are scored and offered, which leaves the answer unchanged: a leaf below it
 // cannot replace the leaf the lane already holds.
-template <int W>
+template <int W, bool kBound = false>
 __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundState* st,
                                         const uint32_t (&y3)[W],
                                         const uint32_t (&z3)[kMaxWN32], uint32_t znz,
@@ -228,7 +228,7 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
   cu32* TA = (cu32*)w.TA;
   cu32* NA = (cu32*)w.NA;
   bool live = valid;
-  if (P.mode == kPruneBound) {
+  if (kBound) {
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < W; ++k) cnt += __popc(y3[k]);
@@ -266,7 +266,7 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
       best.offer(sc, tp, fp, a3, b3, c, d);
       // a best from this prefix has a smaller tuple than its later leaves
       thr = min_tp_for(P, best.s, pre < (best.t >> 16));
-      if (P.mode == kPruneBound) {
+      if (kBound) {
         const unsigned long long key = leaf_key(sc, a3, b3);
         if (key > inc) {
           const unsigned long long old = atomicMax(&st->incumbent, key);

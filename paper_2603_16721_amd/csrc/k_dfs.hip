@@ -39,7 +39,7 @@ namespace {
 
 // Depth-4 pass over n <= 64 staged prefixes (queue entries lane | c << 6,
 // ascending c): prefix s's y2 and z2 come from lane s by cross-lane reads.
-template <int W>
+template <int W, bool kBound>
 __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundState* st,
                                        const uint32_t* q, int n, const uint32_t (&y2)[W],
                                        const uint32_t (&z2)[kMaxWN32], int a, int b, Best& best,
@@ -71,10 +71,12 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
   // visited at depth 4 below the prefix: sorted indices in (idx(c), G-1]
   if (valid) tl.vis4 += (unsigned long long)(P.G - 1 - w.act[c]);
   const int c_first = uniform((int)(q[0] >> 6));
-  expand4<W>(P, w, st, y3, z3, znz, valid, a3, b3, c, c_first, best, tl, inc);
+  expand4<W, kBound>(P, w, st, y3, z3, znz, valid, a3, b3, c, c_first, best, tl, inc);
 }
 
-template <int H, int W64>
+// kBound: bound pruning (Sec. III-E) compiled in; the other modes run the
+// instantiation without it.
+template <int H, int W64, bool kBound>
 __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
   // Narrow rows (<= 8 words): KG consecutive candidate rows arrive with one
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
     const int b = (int)((e >> 16) & 0xffff);
     const int ct = (int)((e >> 32) & 0xffff);
     valid = valid && a < b && b < nA_all;   // list entries always satisfy this
-    if (P.mode == kPruneBound) {
+    if (kBound) {
       inc = load_incumbent(st);
       const bool drop = valid && dominated(P.p * ct + P.q * P.n_normal, a, b, inc);
       if (first_chunk) {
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
           const int tp = popc_and<W>(y2, row);
           const int sc = P.p * tp + P.q * (P.n_normal - fp);
           best.offer(sc, tp, fp, a, b, c, 0);
-          if (P.mode == kPruneBound) {
+          if (kBound) {
             const unsigned long long key = leaf_key(sc, a, b);
             if (key > inc) {
               const unsigned long long old = atomicMax(&st->incumbent, key);
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
         }
         return;
       }
-      if (P.mode == kPruneBound) {
+      if (kBound) {
         bool drop = false;
         if (hit) {
           const int cnt = popc_and<W>(y2, row);
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
       }
       int off = 0;
       while (qn - off >= kWave) {
-        depth4<W>(P, w, st, q + off, kWave, y2, z2, a, b, best, tl, inc, lane);
+        depth4<W, kBound>(P, w, st, q + off, kWave, y2, z2, a, b, best, tl, inc, lane);
         off += kWave;
       }
       if (off > 0) {
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
       }
     }
     if (H == 4 && qn > 0) {
-      depth4<W>(P, w, st, q, qn, y2, z2, a, b, best, tl, inc, lane);
+      depth4<W, kBound>(P, w, st, q, qn, y2, z2, a, b, best, tl, inc, lane);
       qn = 0;
     }
   }
@@ -552,12 +554,13 @@ __global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
 
 // Blocks of one DFS instantiation resident per compute unit (register use
 // differs by row width), queried once.
-template <int H, int W64>
+template <int H, int W64, bool kBound>
 int resident_blocks() {
   static const int n = [] {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&k_dfs<H, W64>), kBlock, 0) != hipSuccess ||
+            &per_cu, reinterpret_cast<const void*>(&k_dfs<H, W64, kBound>), kBlock, 0) !=
+            hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     return per_cu;
@@ -565,12 +568,18 @@ int resident_blocks() {
   return n;
 }
 
+template <int H, int W64, bool kBound>
+hipError_t launch_mode(const Problem& P, const Work& w, int phase, hipStream_t s) {
+  int blocks = resident_blocks<H, W64, kBound>() * (P.n_cu > 0 ? P.n_cu : 1);
+  if (blocks > kPersistBlocks) blocks = kPersistBlocks;
+  k_dfs<H, W64, kBound><<<blocks, kBlock, 0, s>>>(P, w, phase);
+  return hipGetLastError();
+}
+
 template <int H, int W64>
 hipError_t launch_one(const Problem& P, const Work& w, int phase, hipStream_t s) {
-  int blocks = resident_blocks<H, W64>() * (P.n_cu > 0 ? P.n_cu : 1);
-  if (blocks > kPersistBlocks) blocks = kPersistBlocks;
-  k_dfs<H, W64><<<blocks, kBlock, 0, s>>>(P, w, phase);
-  return hipGetLastError();
+  return P.mode == kPruneBound ? launch_mode<H, W64, true>(P, w, phase, s)
+                               : launch_mode<H, W64, false>(P, w, phase, s);
 }
 
 template <int H>
