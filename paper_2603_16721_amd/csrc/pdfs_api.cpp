@@ -525,6 +525,7 @@ int32_t run_records(pdfs_ctx* c, pdfs_combo* out, int32_t cap, int32_t* rounds) 
 }
 
 size_t footprint_bytes(int G, int n_tumor, int n_normal, int nA_max, int h, int prune_mode) {
+  if (prune_mode == PDFS_PRUNE_NONE) nA_max = G;   // exhaustive mode: every gene is a row
   const size_t wt = (size_t)words(n_tumor), wn = (size_t)(n_normal > 0 ? words(n_normal) : 1);
   const size_t rows = (size_t)((nA_max + 127) / 128 * 128 + 128);
   const int w64max = dfs_row_words((int)wt);
