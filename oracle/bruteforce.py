@@ -22,8 +22,11 @@ def sparse_first_order(tumor: np.ndarray, normal: np.ndarray) -> np.ndarray:
     return np.lexsort((np.arange(tumor.shape[0]), counts)).astype(np.int32)
 
 
-def best(tumor, normal, h, p, q, uncovered):
-    """Returns (sorted_idx tuple, tp, fp, score) or None; tumor/normal are bool."""
+def best(tumor, normal, h, p, q, uncovered, tn="all"):
+    """Returns (sorted_idx tuple, tp, fp, score) or None; tumor/normal are bool.
+    tn = "all": a normal counts as a false positive when it carries every gene
+    of the subset; "literal": when it carries any of them (TN = normals with
+    none of the genes)."""
     tumor = np.asarray(tumor, dtype=bool)
     normal = np.asarray(normal, dtype=bool)
     order = sparse_first_order(tumor, normal)
@@ -36,14 +39,15 @@ def best(tumor, normal, h, p, q, uncovered):
         tp = int(np.all(Tu[c], axis=0).sum())
         if tp == 0:
             continue
-        fp = int(np.all(Ns[c], axis=0).sum()) if n_normal else 0
+        hitn = np.any(Ns[c], axis=0) if tn == "literal" else np.all(Ns[c], axis=0)
+        fp = int(hitn.sum()) if n_normal else 0
         s = p * tp + q * (n_normal - fp)
         if best_key is None or s > best_key[3]:
             best_key = (combo, tp, fp, s)
     return best_key
 
 
-def wsc(tumor, normal, h, p, q, target=0, max_rounds=0):
+def wsc(tumor, normal, h, p, q, target=0, max_rounds=0, tn="all"):
     """Greedy loop (Alg. 1) on top of brute-force rounds."""
     tumor = np.asarray(tumor, dtype=bool)
     n_tumor = tumor.shape[1]
@@ -52,7 +56,7 @@ def wsc(tumor, normal, h, p, q, target=0, max_rounds=0):
     K = target if target > 0 else n_tumor
     out = []
     while (n_tumor - unc.sum()) < K and (max_rounds <= 0 or len(out) < max_rounds):
-        b = best(tumor, normal, h, p, q, unc)
+        b = best(tumor, normal, h, p, q, unc, tn)
         if b is None:
             break
         combo, tp, fp, s = b

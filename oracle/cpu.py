@@ -17,6 +17,13 @@ SRC = os.path.join(HERE, "pdfs_oracle.c")
 LIB = os.path.join(HERE, "libpdfs_oracle.so")
 MAX_H = 8
 MODES = {"none": 0, "empty": 1, "bound": 2}
+TN_LITERAL = 0x100   # mode bit: TN = normals carrying none of the genes (literal T-)
+
+
+def _mode(mode, tn):
+    if tn not in ("all", "literal"):
+        raise ValueError("tn must be 'all' or 'literal'")
+    return MODES[mode] | (TN_LITERAL if tn == "literal" else 0)
 
 
 def build() -> str:
@@ -100,7 +107,8 @@ class Best:
     counters: dict
 
 
-def best(T, N, n_tumor, n_normal, h, p, q, U=None, mode="empty", perm=None, L=None) -> Best:
+def best(T, N, n_tumor, n_normal, h, p, q, U=None, mode="empty", perm=None, L=None,
+         tn="all") -> Best:
     T, N = _words(T), _words(N)
     G, wt = T.shape
     if perm is None:
@@ -114,7 +122,7 @@ def best(T, N, n_tumor, n_normal, h, p, q, U=None, mode="empty", perm=None, L=No
     fp = np.zeros(1, dtype=np.int64)
     cnt = np.zeros(3 * (MAX_H + 1), dtype=np.uint64)
     r = (L or lib()).oracle_best(G, n_tumor, n_normal, wt, _ptr(T), N.shape[1], _ptr(N), _ptr(perm),
-                          h, p, q, _ptr(U), MODES[mode], _ptr(idx), _ptr(tp), _ptr(fp),
+                          h, p, q, _ptr(U), _mode(mode, tn), _ptr(idx), _ptr(tp), _ptr(fp),
                           _ptr(cnt))
     if r < 0:
         raise ValueError("oracle_best: invalid arguments")
@@ -127,7 +135,7 @@ def best(T, N, n_tumor, n_normal, h, p, q, U=None, mode="empty", perm=None, L=No
 
 
 def best_share(T, N, n_tumor, n_normal, h, p, q, g1_lo, g1_hi, U=None, mode="empty",
-               perm=None, L=None) -> Best:
+               perm=None, L=None, tn="all") -> Best:
     """One round restricted to first genes in sorted positions [g1_lo, g1_hi)."""
     T, N = _words(T), _words(N)
     G, wt = T.shape
@@ -140,7 +148,7 @@ def best_share(T, N, n_tumor, n_normal, h, p, q, g1_lo, g1_hi, U=None, mode="emp
     fp = np.zeros(1, dtype=np.int64)
     cnt = np.zeros(3 * (MAX_H + 1), dtype=np.uint64)
     r = (L or lib()).oracle_best_share(G, n_tumor, n_normal, wt, _ptr(T), N.shape[1], _ptr(N),
-                                       _ptr(perm), h, p, q, _ptr(U), MODES[mode], g1_lo, g1_hi,
+                                       _ptr(perm), h, p, q, _ptr(U), _mode(mode, tn), g1_lo, g1_hi,
                                        _ptr(idx), _ptr(tp), _ptr(fp), _ptr(cnt))
     if r < 0:
         raise ValueError("oracle_best_share: invalid arguments")
@@ -167,7 +175,7 @@ class WscResult:
 
 
 def wsc(T, N, n_tumor, n_normal, h, p=1, q=10, target=0, max_rounds=0, U0=None,
-        mode="bound", cap=4096, L=None) -> WscResult:
+        mode="bound", cap=4096, L=None, tn="all") -> WscResult:
     T, N = _words(T), _words(N)
     G, wt = T.shape
     genes = np.zeros(cap * h, dtype=np.int32)
@@ -177,7 +185,7 @@ def wsc(T, N, n_tumor, n_normal, h, p=1, q=10, target=0, max_rounds=0, U0=None,
     Uo = np.zeros(wt, dtype=np.uint64)
     U0a = None if U0 is None else np.ascontiguousarray(U0, dtype=np.uint64)
     r = (L or lib()).oracle_wsc(G, n_tumor, n_normal, wt, _ptr(T), N.shape[1], _ptr(N), h, p, q,
-                         target, max_rounds, _ptr(U0a), MODES[mode], cap, _ptr(genes),
+                         target, max_rounds, _ptr(U0a), _mode(mode, tn), cap, _ptr(genes),
                          _ptr(sidx), _ptr(rec), _ptr(cnt), _ptr(Uo))
     if r < 0:
         raise ValueError("oracle_wsc: invalid arguments")

@@ -15,7 +15,10 @@
  *    the running tumour intersection y_l = U & x_g1 & ... & x_gl and
  *    backtracking as soon as it is empty.  At depth h a non-empty y_h is a
  *    candidate; its score is S = p*TP + q*TN with TP = |y_h|,
- *    FP = |n_g1 & ... & n_gh| over all normals, TN = N_n - FP.  S is the
+ *    FP = |n_g1 & ... & n_gh| over all normals, TN = N_n - FP (the normals
+ *    that do not carry the whole combination; with bit 8 of the mode set,
+ *    the literal wording of T- in Sec. II-C instead: TN = normals carrying
+ *    none of the genes, FP = |n_g1 | ... | n_gh|).  S is the
  *    numerator of F = (alpha*TP + TN)/(N_t + N_n) scaled by q, with
  *    alpha = p/q; the denominator is the same for every candidate of a round
  *    so it never changes the argmax.  The strict ">" of the maximum search
@@ -82,6 +85,7 @@ void oracle_order(int32_t G, int32_t wt, const uint64_t *T, int32_t wn,
 /* ------------------------------------------------------------ P-DFS */
 typedef struct {
     int32_t G, wt, wn, n_normal, h, mode;
+    int32_t tn_literal;         /* TN = normals carrying none of the genes */
     const uint64_t *T, *N;
     const int32_t *perm;
     int64_t p, q;
@@ -101,7 +105,12 @@ static void score_leaf(or_dfs *st, int64_t tp) {
         for (int w = 0; w < st->wn; w++) st->z[w] = n0[w];
         for (int l = 1; l < st->h; l++) {
             const uint64_t *nl = st->N + (size_t)st->perm[st->idx[l]] * st->wn;
-            for (int w = 0; w < st->wn; w++) st->z[w] &= nl[w];
+            /* FP: normals carrying every gene of the tuple (AND), or under the
+             * literal reading of T- any of them (OR) */
+            if (st->tn_literal)
+                for (int w = 0; w < st->wn; w++) st->z[w] |= nl[w];
+            else
+                for (int w = 0; w < st->wn; w++) st->z[w] &= nl[w];
         }
         fp = count_bits(st->z, st->wn);
     }
@@ -190,7 +199,9 @@ static int best_share(int32_t G, int32_t n_tumor, int32_t n_normal, int32_t wt,
     (void)n_tumor;
     or_dfs st;
     memset(&st, 0, sizeof(st));
-    st.G = G; st.wt = wt; st.wn = wn; st.n_normal = n_normal; st.h = h; st.mode = mode;
+    st.G = G; st.wt = wt; st.wn = wn; st.n_normal = n_normal; st.h = h;
+    st.mode = mode & 0xff;                  /* bit 8: literal-T- reading */
+    st.tn_literal = (mode >> 8) & 1;
     st.T = T; st.N = N; st.perm = perm; st.p = p; st.q = q;
     st.y = (uint64_t *)calloc((size_t)(h + 1) * wt, sizeof(uint64_t));
     st.z = (uint64_t *)calloc((size_t)(wn > 0 ? wn : 1), sizeof(uint64_t));

@@ -74,6 +74,52 @@ def test_wsc_matches_bruteforce(case):
             assert (a["tp"], a["fp"], a["score_num"]) == (b["tp"], b["fp"], b["score_num"])
 
 
+@pytest.mark.parametrize("case", TINY_CASES)
+@pytest.mark.parametrize("mode", ["none", "empty", "bound"])
+def test_literal_tn_matches_bruteforce(case, mode):
+    """The literal reading of T- (TN = normals carrying none of the genes,
+    Sec. II-C wording): the walk's rounds equal the brute-force definition
+    with FP counted as normals carrying any gene."""
+    I = _tiny(case)
+    T, N = I.packed()
+    r = cpu.wsc(T, N, I.n_tumor, I.n_normal, I.h, I.alpha_p, I.alpha_q, mode=mode, tn="literal")
+    ref = bf.wsc(I.tumor, I.normal, I.h, I.alpha_p, I.alpha_q, tn="literal")
+    assert len(r.rounds) == len(ref)
+    for a, b in zip(r.rounds, ref):
+        assert a["genes"] == b["genes"] and a["sorted_idx"] == b["sorted_idx"]
+        assert (a["tp"], a["fp"], a["score_num"]) == (b["tp"], b["fp"], b["score_num"])
+
+
+def test_literal_tn_hand_example():
+    # Three genes carried by tumours 0 and 1 (every pair: TP 2).  Normals:
+    # gene 0 {0, 1}, gene 1 {2, 3}, gene 2 {0, 1}.  Carrying every gene of a
+    # pair: (0,1) none, (0,2) {0,1}, (1,2) none -> the smaller tuple (0,1)
+    # with FP 0.  Carrying any gene: (0,1) 4, (0,2) {0,1} = 2, (1,2) 4 ->
+    # (0,2) with FP 2.  Equal combined counts keep the caller order.
+    tumor = np.array([[1, 1, 0, 0],
+                      [1, 1, 0, 0],
+                      [1, 1, 0, 0]], dtype=bool)
+    normal = np.array([[1, 1, 0, 0],
+                       [0, 0, 1, 1],
+                       [1, 1, 0, 0]], dtype=bool)
+    T, N = synth.pack_rows(tumor), synth.pack_rows(normal)
+    for tn, genes, fp in (("all", [0, 1], 0), ("literal", [0, 2], 2)):
+        r = cpu.wsc(T, N, 4, 4, 2, 1, 10, mode="empty", tn=tn, max_rounds=1)
+        assert r.rounds[0]["genes"] == genes and r.rounds[0]["fp"] == fp
+        assert r.rounds[0]["tp"] == 2
+        ref = bf.best(tumor, normal, 2, 1, 10, np.ones(4, bool), tn)
+        assert list(ref[0]) == genes and ref[2] == fp
+
+
+def test_literal_tn_single_gene_is_the_same():
+    # for h = 1 "carries the gene" is the same under both readings
+    I = synth.random_tiny(41, 30, 90, 40, 0.2, 1)
+    T, N = I.packed()
+    a = cpu.wsc(T, N, 90, 40, 1, 1, 10, mode="empty")
+    b = cpu.wsc(T, N, 90, 40, 1, 1, 10, mode="empty", tn="literal")
+    assert a.rounds == b.rounds
+
+
 @pytest.mark.parametrize("case", TINY_CASES[:7])
 def test_empty_counters_match_enumeration(case):
     """Per-depth visited / non-empty counts of the EMPTY walk equal a direct
