@@ -330,12 +330,13 @@ def main():
     if not args.no_heldout:
         from paper_2603_16721_amd import heldout
         held = {}
-        for name in ("h3_G5000", "h4_G20000"):
+        for name, lit in (("h3_G5000", False), ("h4_G20000", False), ("h3_G5000", True)):
             wi = inst if name == args.workload else synth.WORKLOADS[name]()
-            r = heldout.learn_and_evaluate(pdfs, wi, 0.25, seed=16721600)
+            r = heldout.learn_and_evaluate(pdfs, wi, 0.25, seed=16721600, tn_literal=lit)
             r.pop("combos")
-            held[name] = r
-            print(f"[bench] held-out {name}: {r['combinations']} combinations, test sensitivity "
+            key = name + ("_tn_literal" if lit else "")
+            held[key] = r
+            print(f"[bench] held-out {key}: {r['combinations']} combinations, test sensitivity "
                   f"{r['test']['sensitivity']:.3f}, specificity {r['test']['specificity']:.3f}",
                   file=sys.stderr, flush=True)
 

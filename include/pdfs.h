@@ -96,6 +96,10 @@ typedef struct {
 /* pdfs_options.flags */
 #define PDFS_OPT_TIME_KERNELS 1   /* time the pair-table and DFS launches with HIP
                                      events on the context's stream (pdfs_stats) */
+#define PDFS_OPT_TN_LITERAL 8     /* TN counts the normals carrying none of the
+                                     combination's genes (the literal wording of
+                                     T- in Sec. II-C; FP = normals carrying any);
+                                     default: normals not carrying all of them */
 #define PDFS_OPT_GRAPHS 2         /* capture one round as a HIP graph per row width
                                      and replay it (needs a non-NULL stream; ignored
                                      together with PDFS_OPT_TIME_KERNELS) */

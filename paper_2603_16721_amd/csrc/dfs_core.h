@@ -82,6 +82,20 @@ __device__ __forceinline__ int popc_and_n(const uint32_t (&z)[kMaxWN32], cu32* r
   return c;
 }
 
+// Normals joined into a prefix: carrying every gene (AND), or under the
+// literal reading of T- any of them (OR).
+__device__ __forceinline__ uint32_t nrm_join(uint32_t a, uint32_t b, bool literal) {
+  return literal ? (a | b) : (a & b);
+}
+
+// FP of a leaf from its prefix's normals z and the last gene's normal row.
+__device__ __forceinline__ int leaf_fp(const uint32_t (&z)[kMaxWN32], cu32* row, bool literal) {
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxWN32; ++k) c += __popc(nrm_join(z[k], row[k], literal));
+  return c;
+}
+
 // sum over k of popcount(y[k] & r[k]) for a row already in (scalar) registers
 template <int W>
 __device__ __forceinline__ int popc_and_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
@@ -238,7 +252,9 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
     live = live && !drop;
     if (!__any(live)) return;
   }
-  const bool zlive = live && znz != 0;
+  // a leaf's FP needs counting unless no normal is left in the prefix (under
+  // the literal reading the last gene's normals add on, so always)
+  const bool zlive = live && (znz != 0 || P.tn_literal);
   if (live) tl.xv4 += (unsigned long long)(nA - 1 - c);
   // a dead lane's TP is 0 at every d: it never counts nor offers
   uint32_t y[W];
@@ -257,7 +273,7 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
     int fp = 0;
     if (__any(hit && zlive)) {
       if (hit && zlive) {
-        fp = popc_and_n(z3, NA + (size_t)d * kMaxWN32);
+        fp = leaf_fp(z3, NA + (size_t)d * kMaxWN32, P.tn_literal);
         tl.xfp++;
       }
     }

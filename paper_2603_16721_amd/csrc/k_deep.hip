@@ -139,11 +139,12 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
         if (P.p * tp + qN < bs) continue;   // cannot reach the lane's best
         uint32_t z[kMaxWN32];
 #pragma unroll
-        for (int k = 0; k < kMaxWN32; ++k) z[k] = ~0u;
+        for (int k = 0; k < kMaxWN32; ++k) z[k] = P.tn_literal ? 0u : ~0u;
         for (int d = 1; d <= h; ++d) {
           const int r = ix[d - 1][lane];
 #pragma unroll
-          for (int k = 0; k < kMaxWN32; ++k) z[k] &= NA[(size_t)r * kMaxWN32 + k];
+          for (int k = 0; k < kMaxWN32; ++k)
+            z[k] = nrm_join(z[k], NA[(size_t)r * kMaxWN32 + k], P.tn_literal);
         }
         int fp = 0;
 #pragma unroll

@@ -63,7 +63,7 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
 #pragma unroll
   for (int k = 0; k < kMaxWN32; ++k) {
     uint32_t v = __shfl(z2[k], s, 64);
-    z3[k] = v & NA[(size_t)cc * kMaxWN32 + k] & vmask;
+    z3[k] = nrm_join(v, NA[(size_t)cc * kMaxWN32 + k], P.tn_literal) & vmask;
     znz |= z3[k];
   }
   const int a3 = __shfl(a, s, 64);
@@ -172,7 +172,8 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
       y2[k] = TA[(size_t)ra * W + k] & TA[(size_t)rb * W + k] & vmask;
 #pragma unroll
     for (int k = 0; k < kMaxWN32; ++k)
-      z2[k] = NA[(size_t)ra * kMaxWN32 + k] & NA[(size_t)rb * kMaxWN32 + k] & vmask;
+      z2[k] = nrm_join(NA[(size_t)ra * kMaxWN32 + k], NA[(size_t)rb * kMaxWN32 + k],
+                       P.tn_literal) & vmask;
     uint32_t znz = 0;
 #pragma unroll
     for (int k = 0; k < kMaxWN32; ++k) znz |= z2[k];
@@ -195,9 +196,10 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
       }
       if (H == 3) {
         int fp = 0;
-        if (__any(hit && znz != 0)) {
-          if (hit && znz != 0) {
-            fp = popc_and_n(z2, NA + (size_t)c * kMaxWN32);
+        const bool zn = znz != 0 || P.tn_literal;
+        if (__any(hit && zn)) {
+          if (hit && zn) {
+            fp = leaf_fp(z2, NA + (size_t)c * kMaxWN32, P.tn_literal);
             tl.xfp++;
           }
         }

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
       const int j = bj * kBT + wc * 64 + n * 32 + col;
       const bool jok = active && j < amax2;
       int sj = 0;
-      if (!kH2 && jok) sj = w.act[j];
+      if (jok && (!kH2 || P.tn_literal)) sj = w.act[j];
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
 #pragma unroll
@@ -166,9 +166,13 @@ __global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
           const bool emit = jok && i < j && i < amax1 && (c > 0 || P.mode == kPruneNone);
           if (kH2) {
             if (ok) {
-              const int s = P.p * c + P.q * (P.n_normal - accn[m][n][r]);
+              // literal reading: normals carrying either gene
+              const int fp = P.tn_literal
+                                 ? w.ncount[w.act[i]] + w.ncount[sj] - accn[m][n][r]
+                                 : accn[m][n][r];
+              const int s = P.p * c + P.q * (P.n_normal - fp);
               if (s > bs || (s == bs && (i < bi_ || (i == bi_ && j < bj_)))) {
-                bs = s; btp = c; bfp = accn[m][n][r]; bi_ = i; bj_ = j;
+                bs = s; btp = c; bfp = fp; bi_ = i; bj_ = j;
               }
             }
           } else if (emit) {

@@ -50,6 +50,15 @@ __global__ void k_gather_sorted(const uint64_t* __restrict__ T, int64_t ts,
   for (int w = 0; w < wn; ++w) Ns[(size_t)i * wn + w] = N ? N[(size_t)g * ns + w] : 0ull;
 }
 
+// Normals carrying each sorted gene (rows are fixed for the cohort).
+__global__ void k_normal_counts(const uint64_t* __restrict__ Ns, int G, int wn, int32_t* ncount) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  int c = 0;
+  for (int k = 0; k < wn; ++k) c += __popcll(Ns[(size_t)g * wn + k]);
+  ncount[g] = c;
+}
+
 __global__ void k_check_pad(const uint64_t* __restrict__ T, int64_t ts, int G, int n,
                             int* __restrict__ bad) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -468,6 +477,12 @@ hipError_t launch_gather_sorted(const uint64_t* T, int64_t ts, const uint64_t* N
                                 const int32_t* perm, int G, int wt, int wn, uint64_t* Ts,
                                 uint64_t* Ns, hipStream_t s) {
   k_gather_sorted<<<(G + 255) / 256, 256, 0, s>>>(T, ts, N, ns, perm, G, wt, wn, Ts, Ns);
+  return hipGetLastError();
+}
+
+hipError_t launch_normal_counts(const uint64_t* Ns, int G, int wn, int32_t* ncount,
+                                hipStream_t s) {
+  k_normal_counts<<<(G + 255) / 256, 256, 0, s>>>(Ns, G, wn, ncount);
   return hipGetLastError();
 }
 

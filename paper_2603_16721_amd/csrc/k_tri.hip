@@ -227,8 +227,9 @@ __global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs4_tiles(Problem
     uint32_t znz = 0;
 #pragma unroll
     for (int k = 0; k < kMaxWN32; ++k) {
-      z3[k] = NA[(size_t)a3 * kMaxWN32 + k] & NA[(size_t)b3 * kMaxWN32 + k] &
-              NA[(size_t)c * kMaxWN32 + k] & vmask;
+      z3[k] = nrm_join(nrm_join(NA[(size_t)a3 * kMaxWN32 + k], NA[(size_t)b3 * kMaxWN32 + k],
+                                P.tn_literal),
+                       NA[(size_t)c * kMaxWN32 + k], P.tn_literal) & vmask;
       znz |= z3[k];
     }
     // visited at depth 4 below the prefix: sorted indices in (idx(c), G-1]

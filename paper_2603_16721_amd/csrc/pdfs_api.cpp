@@ -54,7 +54,7 @@ hipError_t dalloc(pdfs_ctx* c, T** p, size_t n) {
 }
 
 void release(pdfs_ctx* c) {
-  void* ptrs[] = {c->Ts, c->Ns, c->perm, c->U, c->cols, c->act, c->flags, c->TA, c->NA,
+  void* ptrs[] = {c->Ts, c->Ns, c->perm, c->ncount, c->U, c->cols, c->act, c->flags, c->TA, c->NA,
                   c->A8, c->N8, c->pairs, c->work_pairs, c->seed_pairs, c->hist,
                   c->items, c->slots, c->tallies, c->st, c->recs, c->tri, c->tri_s,
                   c->c_hist};
@@ -127,6 +127,7 @@ int32_t ensure_workspace(pdfs_ctx* c, int h) {
 Work make_work(pdfs_ctx* c, int w64, int target) {
   Work w;
   w.Ts = c->Ts; w.Ns = c->Ns; w.perm = c->perm; w.U = c->U; w.cols = c->cols; w.act = c->act;
+  w.ncount = c->ncount;
   w.flags = c->flags; w.TA = c->TA; w.NA = c->NA; w.A8 = c->A8; w.N8 = c->N8;
   w.pairs = c->pairs;
   w.work_pairs = (c->prune_mode == PDFS_PRUNE_BOUND && c->work_pairs) ? c->work_pairs : c->pairs;
@@ -146,6 +147,7 @@ Problem make_problem(const pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
   P.G = c->G; P.n_tumor = c->n_tumor; P.n_normal = c->n_normal; P.wt = c->wt; P.wn = c->wn;
   P.h = h; P.p = (int32_t)p; P.q = (int32_t)q; P.mode = c->prune_mode;
   P.n_cu = c->n_cu;
+  P.tn_literal = c->tn_literal ? 1 : 0;
   return P;
 }
 
@@ -629,6 +631,7 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   c->async_alloc = async_alloc && c->stream != nullptr;
   c->prune_mode = mode;
   c->time_kernels = opt && (opt->flags & PDFS_OPT_TIME_KERNELS);
+  c->tn_literal = opt && (opt->flags & PDFS_OPT_TN_LITERAL);
   c->G = m->G; c->n_tumor = m->n_tumor; c->n_normal = m->n_normal;
   c->wt = wt; c->wn = wn_in > 0 ? wn_in : 1;
   c->w64_max = pdfs::dfs_row_words(wt);
@@ -715,6 +718,8 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   CKC(dalloc(c, &c->Ns, (size_t)G * c->wn));
   CKC(launch_gather_sorted(dT, m->tumor_stride_words, dN, m->normal_stride_words, c->perm, G, wt,
                            c->wn, c->Ts, c->Ns, s));
+  CKC(dalloc(c, &c->ncount, (size_t)G));
+  CKC(launch_normal_counts(c->Ns, G, c->wn, c->ncount, s));
   c->h_perm.resize(G);
   CKC(hipMemcpyAsync(c->h_perm.data(), c->perm, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
   std::vector<uint32_t> h_counts(G);
@@ -750,7 +755,7 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   {
     Problem P;
     P.G = G; P.n_tumor = m->n_tumor; P.n_normal = m->n_normal; P.wt = wt; P.wn = c->wn;
-    P.h = 1; P.p = 1; P.q = 1; P.mode = mode; P.n_cu = c->n_cu;
+    P.h = 1; P.p = 1; P.q = 1; P.mode = mode; P.n_cu = c->n_cu; P.tn_literal = 0;
     Work w = make_work(c, 1, 0);
     CKC(launch_fill_u(c->U, wt, m->n_tumor, s));
     CKC(launch_round_begin(P, w, s));

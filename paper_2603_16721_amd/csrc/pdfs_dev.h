@@ -134,6 +134,7 @@ struct Problem {
   int32_t p, q;
   int32_t mode;
   int32_t n_cu;   // compute units of the device (sizes the persistent DFS grid)
+  int32_t tn_literal;   // FP = normals carrying any gene (else: carrying all)
 };
 
 // Round workspace pointers.
@@ -144,6 +145,7 @@ struct Work {
   uint64_t* U;
   int32_t* cols;
   int32_t* act;
+  const int32_t* ncount;            // [G] normals carrying each sorted gene
   uint8_t* flags;
   uint32_t* TA;
   uint32_t* NA;
@@ -183,6 +185,8 @@ hipError_t sort_genes(uint32_t* counts, uint32_t* counts_tmp, int32_t* ids, int3
 hipError_t launch_gather_sorted(const uint64_t* T, int64_t ts, const uint64_t* N, int64_t ns,
                                 const int32_t* perm, int G, int wt, int wn, uint64_t* Ts,
                                 uint64_t* Ns, hipStream_t s);
+hipError_t launch_normal_counts(const uint64_t* Ns, int G, int wn, int32_t* ncount,
+                                hipStream_t s);
 hipError_t launch_check_pad(const uint64_t* T, int64_t ts, int G, int n, int* bad, hipStream_t s);
 
 // per round

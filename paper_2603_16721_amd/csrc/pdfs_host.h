@@ -46,6 +46,8 @@ struct pdfs_ctx {
   uint64_t* Ts = nullptr;
   uint64_t* Ns = nullptr;
   int32_t* perm = nullptr;
+  int32_t* ncount = nullptr;           // normals carrying each sorted gene
+  bool tn_literal = false;             // PDFS_OPT_TN_LITERAL
   uint64_t* U = nullptr;
   int32_t* cols = nullptr;
   int32_t* act = nullptr;

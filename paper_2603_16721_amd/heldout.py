@@ -59,9 +59,10 @@ def coverage_report(combos, tumor: np.ndarray, normal: np.ndarray) -> dict:
 
 
 def learn_and_evaluate(pdfs, inst: synth.Instance, test_frac: float = 0.25, seed: int = 0,
-                       prune_mode: str = "bound") -> dict:
+                       prune_mode: str = "bound", tn_literal: bool = False) -> dict:
     """Split, learn the cover on the training split with the GPU path
-    (`pdfs` is the binding module), report both splits."""
+    (`pdfs` is the binding module), report both splits.  tn_literal: learn
+    with the literal reading of T- (TN = normals carrying none of the genes)."""
     parts = split_cohort(inst, test_frac, seed)
     t_tr, n_tr = parts["train"]
     T, N = synth.pack_rows(t_tr), synth.pack_rows(n_tr)
@@ -70,10 +71,11 @@ def learn_and_evaluate(pdfs, inst: synth.Instance, test_frac: float = 0.25, seed
     if inst.target_covered:
         target = int(np.ceil(inst.target_covered * t_tr.shape[1] / inst.n_tumor))
     with pdfs.Solver(T, N if n_tr.shape[1] else None, t_tr.shape[1], n_tr.shape[1],
-                     prune_mode) as sv:
+                     prune_mode, tn_literal=tn_literal) as sv:
         rounds, _, _ = sv.wsc(inst.h, inst.alpha_p, inst.alpha_q, target=target)
     combos = [r["genes"] for r in rounds]
     return {"combinations": len(combos), "h": inst.h, "split_seed": seed, "target": target,
+            "tn": "literal" if tn_literal else "all",
             "train_tp_sum": sum(r["tp"] for r in rounds),
             "train": coverage_report(combos, *parts["train"]),
             "test": coverage_report(combos, *parts["test"]),

@@ -74,6 +74,7 @@ EXPORTS = ["pdfs_create", "pdfs_destroy", "pdfs_set_prune_mode", "pdfs_best_comb
            "pdfs_server_destroy", "pdfs_measure_int_peak"]
 PDFS_OPT_GRAPHS = 2
 PDFS_OPT_AUTOTUNE = 4
+PDFS_OPT_TN_LITERAL = 8
 
 
 def _load():
@@ -253,12 +254,13 @@ class Solver:
     """Owns one context for a cohort (packed uint64 rows, LSB-first samples)."""
 
     def __init__(self, tumor, normal, n_tumor, n_normal, prune_mode="bound", device=0,
-                 stream=None, time_kernels=False):
+                 stream=None, time_kernels=False, tn_literal=False):
         self.n_tumor = n_tumor
         self.n_normal = n_normal
         self.ctx = None
-        self.ctx = pdfs_create(tumor, normal, n_tumor, n_normal, prune_mode, device, stream,
-                               PDFS_OPT_TIME_KERNELS if time_kernels else 0)
+        flags = (PDFS_OPT_TIME_KERNELS if time_kernels else 0) | \
+            (PDFS_OPT_TN_LITERAL if tn_literal else 0)
+        self.ctx = pdfs_create(tumor, normal, n_tumor, n_normal, prune_mode, device, stream, flags)
 
     def close(self):
         if self.ctx:

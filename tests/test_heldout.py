@@ -65,3 +65,23 @@ def test_learn_on_gpu_matches_oracle(name):
     assert out["train"]["TC"] == out["train_tp_sum"]
     assert out["train"]["TT"] + out["test"]["TT"] == 160
     assert out["train"]["NT"] + out["test"]["NT"] == 60
+
+
+@pytest.mark.gpu
+def test_learn_literal_tn_on_gpu_matches_oracle():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_16721_amd import pdfs
+    I = synth.random_tiny(45, 80, 160, 60, 0.1, 3)
+    out = heldout.learn_and_evaluate(pdfs, I, 0.25, seed=9, tn_literal=True)
+    t_tr, n_tr = heldout.split_cohort(I, 0.25, 9)["train"]
+    exp = cpu.wsc(synth.pack_rows(t_tr), synth.pack_rows(n_tr), t_tr.shape[1], n_tr.shape[1],
+                  3, 1, 10, mode="empty", tn="literal")
+    assert out["combos"] == [r["genes"] for r in exp.rounds]
+    # under the literal reading a combination's FP is the normals carrying any gene
+    for r in exp.rounds:
+        carried = np.zeros(n_tr.shape[1], dtype=bool)
+        for g in r["genes"]:
+            carried |= n_tr[g]
+        assert int(carried.sum()) == r["fp"]
