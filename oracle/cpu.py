@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pdfs_oracle.c")
 LIB = os.path.join(HERE, "libpdfs_oracle.so")
-MAX_H = 8
+MAX_H = 9
 MODES = {"none": 0, "empty": 1, "bound": 2}
 TN_LITERAL = 0x100   # mode bit: TN = normals carrying none of the genes (literal T-)
 

@@ -46,7 +46,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OR_MAX_H 8
+#define OR_MAX_H 9
 
 enum { OR_MODE_NONE = 0, OR_MODE_EMPTY = 1, OR_MODE_BOUND = 2 };
 

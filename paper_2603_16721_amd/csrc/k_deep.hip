@@ -1,4 +1,4 @@
-// Depth-first expansion for h = 5..8 (Alg. 2 depths 3..h, Sec. III-C).
+// Depth-first expansion for h = 5..9 (Alg. 2 depths 3..h, Sec. III-C).
 //
 // Work unit as for h <= 4: 64 non-empty pairs (one per lane) x a range of
 // depth-3 candidates.  Each lane walks its pair's subtree in Alg. 2's order

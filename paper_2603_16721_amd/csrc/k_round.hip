@@ -331,7 +331,7 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
     __syncthreads();
   }
   Slot b;
-  b.s = -1; b.tp = b.fp = 0; b.pad = 0;
+  b.s = -1; b.tp = b.fp = 0;
   for (int i = 0; i < kMaxH; ++i) b.idx[i] = 0;
   for (int ph = 0; ph < kSlotPhases; ++ph) {
     if (!((phase_mask >> ph) & 1)) continue;

@@ -24,7 +24,7 @@
 
 namespace pdfs {
 
-constexpr int kMaxH = 8;
+constexpr int kMaxH = 9;
 constexpr int kWave = 64;
 constexpr int kMaxW64 = 20;        // tumour words per row the DFS kernels take
 constexpr int kMaxWN32 = 16;       // normal 32-bit words per row (n_normal <= 512)
@@ -117,7 +117,6 @@ struct Slot {
   int32_t s;             // score, -1 = empty
   int32_t tp, fp;
   int32_t idx[kMaxH];    // active-list indices, ascending (zero past h)
-  int32_t pad;
 };
 
 struct Item {
@@ -201,7 +200,7 @@ hipError_t launch_make_items(const Problem& P, const Work& w, bool seed, hipStre
 hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s);
 hipError_t launch_use_all_pairs(const Work& w, hipStream_t s);
 hipError_t launch_dfs(const Problem& P, const Work& w, int phase, hipStream_t s);
-// h = 5..8: per-lane subtree walk with an index stack (main phase only)
+// h = 5..9: per-lane subtree walk with an index stack (main phase only)
 hipError_t launch_dfs_deep(const Problem& P, const Work& w, hipStream_t s);
 // two-phase depth-4 (h = 4, empty-prefix pruning): the main DFS lists the
 // non-empty depth-3 prefixes with long candidate streams, they are bucketed

@@ -15,7 +15,7 @@ __device__ __forceinline__ bool slot_better(const Slot& c, const Slot& b) {
 
 __device__ __forceinline__ Slot empty_slot() {
   Slot e;
-  e.s = -1; e.tp = e.fp = 0; e.pad = 0;
+  e.s = -1; e.tp = e.fp = 0;
   for (int i = 0; i < kMaxH; ++i) e.idx[i] = 0;
   return e;
 }
@@ -27,7 +27,6 @@ __device__ __forceinline__ Slot wave_best(Slot b) {
     c.tp = __shfl_xor(b.tp, o, 64);
     c.fp = __shfl_xor(b.fp, o, 64);
     for (int i = 0; i < kMaxH; ++i) c.idx[i] = __shfl_xor(b.idx[i], o, 64);
-    c.pad = 0;
     if (slot_better(c, b)) b = c;
   }
   return b;

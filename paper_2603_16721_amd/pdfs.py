@@ -28,7 +28,7 @@ PDFS_PRUNE_NONE = 0
 PDFS_PRUNE_EMPTY = 1
 PDFS_PRUNE_BOUND = 2
 PRUNE_MODES = {"none": PDFS_PRUNE_NONE, "empty": PDFS_PRUNE_EMPTY, "bound": PDFS_PRUNE_BOUND}
-MAX_H = 8
+MAX_H = 9
 
 
 class pdfs_matrix(ctypes.Structure):

@@ -78,7 +78,7 @@ def test_wsc_tiny(pdfs, case, mode):
         _counters_equal(stats, exp.counters, h)
 
 
-# h = 5..8: the per-lane subtree walk (every mode; BOUND runs the same walk)
+# h = 5..9: the per-lane subtree walk (every mode; BOUND runs the same walk)
 DEEP = [
     # seed, G, n_tumor, n_normal, density, h, alpha
     (201, 40, 100, 30, 0.25, 5, (1, 10)),
@@ -87,6 +87,9 @@ DEEP = [
     (204, 20, 64, 64, 0.5, 8, (1, 10)),
     (205, 60, 200, 40, 0.15, 5, (3, 7)),
     (206, 36, 130, 0, 0.3, 6, (0, 1)),
+    (207, 18, 96, 40, 0.6, 9, (1, 10)),
+    (208, 22, 70, 20, 0.55, 9, (2, 5)),
+    (209, 9, 64, 10, 0.9, 9, (1, 10)),    # h = G: one subset
 ]
 
 

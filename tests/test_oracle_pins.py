@@ -31,6 +31,7 @@ TINY_CASES = [
     (8, 8, 128, 1, 0.50, 1, (1, 10)),
     (9, 12, 200, 70, 0.35, 4, (1, 10)),
     (10, 7, 33, 17, 0.6, 5, (2, 3)),
+    (11, 11, 90, 40, 0.7, 9, (1, 10)),
 ]
 
 
@@ -155,7 +156,7 @@ def test_table1_closed_form():
         assert f"{mant / 100:.2f}e{e}" == f"{v:.2e}".replace("e+", "e").replace("e0", "e"), (h, exact, v)
 
 
-@pytest.mark.parametrize("G,h", [(9, 1), (10, 2), (11, 3), (12, 4), (10, 5)])
+@pytest.mark.parametrize("G,h", [(9, 1), (10, 2), (11, 3), (12, 4), (10, 5), (12, 9)])
 def test_exhaustive_visits_all_subsets(G, h):
     """The pruning-off baseline visits exactly C(G,h) leaves (the quantity of
     Table I), and C(G,l)-style counts at inner depths."""
