@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-exhaustive", action="store_true",
                     help="skip the pruned-vs-exhaustive first-round comparison")
+    ap.add_argument("--no-deep", action="store_true",
+                    help="skip the h = 5, 6 first-round report")
     ap.add_argument("--no-heldout", action="store_true",
                     help="skip the 75/25 held-out coverage report")
     ap.add_argument("--served-requests", type=int, default=400)
@@ -324,6 +326,31 @@ def main():
                   f"{row['none']['round1_ms']:.2f} ms vs {row['empty']['round1_ms']:.2f} ms",
                   file=sys.stderr, flush=True)
 
+    # ---- deeper combinations (h = 5, 6) on the h3_G5000 cohort, first greedy
+    # round: the per-lane subtree walk below the pair level
+    deep = None
+    if not args.no_deep:
+        deep = {}
+        wi = synth.WORKLOADS["h3_G5000"]()
+        Ti, Ni = wi.packed()
+        svx = pdfs.Solver(Ti, Ni, wi.n_tumor, wi.n_normal, "empty", 0, stream.cuda_stream)
+        for hd in (5, 6):
+            svx.wsc(hd, wi.alpha_p, wi.alpha_q, max_rounds=1)
+            torch.cuda.synchronize()
+            tx = time.perf_counter()
+            r1, st1, _ = svx.wsc(hd, wi.alpha_p, wi.alpha_q, max_rounds=1)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - tx
+            deep[f"h{hd}_G5000_round1"] = {
+                "round1_ms": 1e3 * dt, "visited": st1["visited"][1:hd + 1],
+                "nonempty": st1["nonempty"][1:hd + 1],
+                "leaf_visits_per_s": st1["visited"][hd] / dt,
+                "genes": r1[0]["genes"] if r1 else None,
+                "tp": r1[0]["tp"] if r1 else None, "fp": r1[0]["fp"] if r1 else None}
+            print(f"[bench] h = {hd} round 1 on h3_G5000: {1e3 * dt:.1f} ms, "
+                  f"{st1['visited'][hd]:.3e} leaf visits", file=sys.stderr, flush=True)
+        svx.close()
+
     # ---- held-out coverage (accuracy protocol): learn on a 75 % split of the
     # samples with the GPU path, score the frozen combinations on both splits
     held = None
@@ -401,6 +428,8 @@ def main():
     }
     if exhaustive is not None:
         out["exhaustive_vs_pruned_round1"] = exhaustive
+    if deep is not None:
+        out["deep_round1"] = deep
     if held is not None:
         out["heldout_75_25"] = held
     if not args.no_batched:

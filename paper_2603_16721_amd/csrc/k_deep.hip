@@ -1,17 +1,25 @@
 // Depth-first expansion for h = 5..9 (Alg. 2 depths 3..h, Sec. III-C).
 //
 // Work unit as for h <= 4: 64 non-empty pairs (one per lane) x a range of
-// depth-3 candidates.  Each lane walks its pair's subtree in Alg. 2's order
-// with an explicit stack: the candidate index of every depth sits in LDS (one
-// column per lane), the running intersection of the parent of the depth
-// being enumerated in VGPRs.  A candidate's intersection is the parent's AND
-// its row; a non-empty one (any one in exhaustive mode) becomes the parent of
-// the next depth, and on the way back up the parent of the shallower depth is
-// rebuilt from the stacked indices (y2 AND the rows of depths 3..l-2), so only
-// one intersection per lane is ever held.  Leaves (depth h) with TP >= 1 are
-// scored S = p*TP + q*(N_n - FP) and compared with the lane's best under
-// (S desc, tuple asc); the normal intersection is formed only for a leaf
-// whose best possible score (FP = 0) reaches the lane's best.
+// depth-3 candidates.  Each lane walks its pair's subtree over depths
+// 3..h-1 in Alg. 2's order with an explicit stack: the candidate index of
+// every depth sits in LDS (one column per lane), the running intersection of
+// the parent of the depth being enumerated in VGPRs.  A candidate's
+// intersection is the parent's AND its row; a non-empty one (any one in
+// exhaustive mode) becomes the parent of the next depth, and on the way back
+// up the parent of the shallower depth is rebuilt from the stacked indices
+// (y2 AND the rows of depths 3..l-2), so only one intersection per lane is
+// ever held.
+//
+// The leaf depth is not walked per lane.  A non-empty depth-(h-1) prefix
+// (its intersection and indices) goes into a ring of the wave in device
+// memory; once 64 are queued the whole wave takes them, one per lane, and
+// streams the leaf candidates c in (min last index, amax_h) through scalar
+// row loads, each lane masking the c at or below its own last index -- the
+// candidate row is loaded once per wave instead of once per lane.  Leaves
+// with TP >= 1 are scored S = p*TP + q*(N_n - FP) and compared with the
+// lane's best under (S desc, tuple asc); the normal join of a prefix is
+// formed only once one of its leaves can reach the lane's best (FP = 0).
 //
 // Counters: non-empty prefixes per depth, and for every extended depth-l
 // prefix the depth-(l+1) visits of Alg. 2's loop bounds (sorted indices in
@@ -32,15 +40,21 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   constexpr int W = 2 * W64;
   __shared__ int stk[kBlock / kWave][kMaxH][kWave];   // candidate index per depth, per lane
   __shared__ int s_amax[kMaxH + 1];
+  // per-lane counters (own column, no atomics): [0] non-empty, [1] visited
+  __shared__ unsigned long long s_cnt[kBlock / kWave][2][kMaxH + 1][kWave];
   RoundState* st = w.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   if (threadIdx.x <= kMaxH) s_amax[threadIdx.x] = st->amax[threadIdx.x];
-  __syncthreads();
   int (*ix)[kWave] = stk[wib];
+  unsigned long long (*cne)[kWave] = s_cnt[wib][0];
+  unsigned long long (*cvis)[kWave] = s_cnt[wib][1];
+  for (int d = 0; d <= kMaxH; ++d) cne[d][lane] = cvis[d][lane] = 0ull;
+  __syncthreads();
   const int h = P.h;
   const bool all_pre = P.mode == kPruneNone;
+  const bool lit = P.tn_literal != 0;
   const unsigned long long* __restrict__ plist = w.work_pairs;
   const unsigned long long npairs = st->n_work_pairs;
   const unsigned long long nit = st->n_items;
@@ -49,15 +63,93 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && nit > w.item_cap) st->overflow |= 1;
   const uint32_t* __restrict__ TA = w.TA;
   const uint32_t* __restrict__ NA = w.NA;
+  cu32* TAc = (cu32*)w.TA;
+  cu32* NAc = (cu32*)w.NA;
   const int qN = P.q * P.n_normal;
+
+  // this wave's leaf-prefix ring: [W][kDeepQ] intersections, [kMaxH][kDeepQ]
+  // indices; qh / qt count entries taken / queued (wave-uniform)
+  uint32_t* __restrict__ qy =
+      w.deepq + (size_t)(blockIdx.x * (kBlock / kWave) + wib) * (size_t)(W + kMaxH) * kDeepQ;
+  int* __restrict__ qix = reinterpret_cast<int*>(qy + (size_t)W * kDeepQ);
+  int qh = 0, qt = 0;
 
   int bs = -1, btp = 0, bfp = 0;
   int bidx[kMaxH];
 #pragma unroll
   for (int i = 0; i < kMaxH; ++i) bidx[i] = 0;
-  unsigned long long ne[kMaxH + 1], vis[kMaxH + 1];
+  unsigned long long ne_leaf = 0;
+
+  // The wave takes `take` (1..64) queued prefixes, one per lane, and scores
+  // their leaves.  Called with every lane of the wave active.
+  auto drain = [&](int take) {
+    // the entries were written by other lanes of this wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const bool v = lane < take;
+    const int e = (qh + lane) & (kDeepQ - 1);
+    uint32_t y[W];
 #pragma unroll
-  for (int d = 0; d <= kMaxH; ++d) ne[d] = vis[d] = 0;
+    for (int k = 0; k < W; ++k) y[k] = v ? qy[(size_t)k * kDeepQ + e] : 0u;
+    int pix[kMaxH];
+    int last = 0x7fffffff;
+#pragma unroll
+    for (int i = 0; i < kMaxH; ++i) {
+      pix[i] = (v && i < h - 1) ? qix[i * kDeepQ + e] : 0;
+      if (v && i == h - 2) last = pix[i];
+    }
+    qh += take;
+    int lo = last == 0x7fffffff ? last : last + 1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lo = min(lo, __shfl_xor(lo, o, 64));
+    lo = uniform(lo);
+    const int hi = s_amax[h];
+    bool zr = false;
+    uint32_t z[kMaxWN32];
+#pragma unroll
+    for (int k = 0; k < kMaxWN32; ++k) z[k] = 0u;
+    for (int c = lo; c < hi; ++c) {
+      const int tp = popc_and<W>(y, TAc + (size_t)c * W);
+      if (!(v && c > last && tp > 0)) continue;
+      ++ne_leaf;
+      if (P.p * tp + qN < bs) continue;   // cannot reach the lane's best
+      if (!zr) {
+#pragma unroll
+        for (int k = 0; k < kMaxWN32; ++k) z[k] = lit ? 0u : ~0u;
+#pragma unroll
+        for (int d = 0; d < kMaxH; ++d) {
+          if (d < h - 1) {
+#pragma unroll
+            for (int k = 0; k < kMaxWN32; ++k)
+              z[k] = nrm_join(z[k], NA[(size_t)pix[d] * kMaxWN32 + k], lit);
+          }
+        }
+        zr = true;
+      }
+      const int fp = leaf_fp(z, NAc + (size_t)c * kMaxWN32, lit);
+      const int s = P.p * tp + P.q * (P.n_normal - fp);
+      bool take_it = s > bs;
+      if (s == bs) {
+        // equal score: the smaller tuple (lexicographic, sorted indices)
+        int cmp = 0;
+#pragma unroll
+        for (int i = 0; i < kMaxH; ++i) {
+          if (cmp == 0 && i < h) {
+            const int x = i < h - 1 ? pix[i] : c;
+            cmp = x < bidx[i] ? -1 : (x > bidx[i] ? 1 : 0);
+          }
+        }
+        take_it = cmp < 0;
+      }
+      if (take_it) {
+        bs = s;
+        btp = tp;
+        bfp = fp;
+#pragma unroll
+        for (int i = 0; i < kMaxH; ++i) bidx[i] = i < h - 1 ? pix[i] : (i == h - 1 ? c : 0);
+      }
+    }
+  };
 
   const uint32_t nwaves = gridDim.x * (kBlock / kWave);
   const uint32_t gw = blockIdx.x * (kBlock / kWave) + wib;
@@ -88,103 +180,80 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
     bool live = valid && lo3 < c_hi;
     if (!__any(live)) continue;
     const int ra = valid ? a : 0, rb = valid ? b : 0;   // in-range rows for idle lanes
-    uint32_t y2[W], yp[W];
+    uint32_t y2[W], yp[W], yc[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
       y2[k] = TA[(size_t)ra * W + k] & TA[(size_t)rb * W + k];
       yp[k] = y2[k];
+      yc[k] = 0u;
     }
     ix[0][lane] = a;
     ix[1][lane] = b;
     ix[2][lane] = lo3 - 1;
     int level = 3;   // the depth whose candidates the lane enumerates
     while (__any(live)) {
-      if (!live) continue;
-      const int l = level;
-      const int cand = ix[l - 1][lane] + 1;
-      const int hi = l == 3 ? c_hi : s_amax[l];
-      if (cand >= hi) {
-        // this depth is exhausted: back to depth l-1, whose candidates'
-        // parent is the intersection of depths 1..l-2
-        if (l == 3) {
-          live = false;
-          continue;
-        }
-        level = l - 1;
-#pragma unroll
-        for (int k = 0; k < W; ++k) yp[k] = y2[k];
-        for (int d = 3; d <= l - 2; ++d) {
-          const int r = ix[d - 1][lane];
-#pragma unroll
-          for (int k = 0; k < W; ++k) yp[k] &= TA[(size_t)r * W + k];
-        }
-        continue;
-      }
-      ix[l - 1][lane] = cand;
-      uint32_t yc[W];
-      uint32_t any = 0;
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        yc[k] = yp[k] & TA[(size_t)cand * W + k];
-        any |= yc[k];
-      }
-#pragma unroll
-      for (int d = 3; d <= kMaxH; ++d)
-        if (d == l && any) ne[d]++;
-      if (l == h) {
-        if (!any) continue;
-        int tp = 0;
-#pragma unroll
-        for (int k = 0; k < W; ++k) tp += __popc(yc[k]);
-        if (P.p * tp + qN < bs) continue;   // cannot reach the lane's best
-        uint32_t z[kMaxWN32];
-#pragma unroll
-        for (int k = 0; k < kMaxWN32; ++k) z[k] = P.tn_literal ? 0u : ~0u;
-        for (int d = 1; d <= h; ++d) {
-          const int r = ix[d - 1][lane];
-#pragma unroll
-          for (int k = 0; k < kMaxWN32; ++k)
-            z[k] = nrm_join(z[k], NA[(size_t)r * kMaxWN32 + k], P.tn_literal);
-        }
-        int fp = 0;
-#pragma unroll
-        for (int k = 0; k < kMaxWN32; ++k) fp += __popc(z[k]);
-        const int s = P.p * tp + P.q * (P.n_normal - fp);
-        bool take = s > bs;
-        if (s == bs) {
-          // equal score: the smaller tuple (lexicographic, sorted indices)
-          int cmp = 0;
-#pragma unroll
-          for (int i = 0; i < kMaxH; ++i) {
-            if (cmp == 0 && i < h) {
-              const int x = ix[i][lane];
-              cmp = x < bidx[i] ? -1 : (x > bidx[i] ? 1 : 0);
-            }
+      bool push = false;   // a non-empty depth-(h-1) prefix in yc / ix
+      do {
+        if (!live) break;
+        const int l = level;
+        const int cand = ix[l - 1][lane] + 1;
+        const int hi = l == 3 ? c_hi : s_amax[l];
+        if (cand >= hi) {
+          // this depth is exhausted: back to depth l-1, whose candidates'
+          // parent is the intersection of depths 1..l-2
+          if (l == 3) {
+            live = false;
+            break;
           }
-          take = cmp < 0;
-        }
-        if (take) {
-          bs = s;
-          btp = tp;
-          bfp = fp;
+          level = l - 1;
 #pragma unroll
-          for (int i = 0; i < kMaxH; ++i) bidx[i] = i < h ? ix[i][lane] : 0;
+          for (int k = 0; k < W; ++k) yp[k] = y2[k];
+          for (int d = 3; d <= l - 2; ++d) {
+            const int r = ix[d - 1][lane];
+#pragma unroll
+            for (int k = 0; k < W; ++k) yp[k] &= TA[(size_t)r * W + k];
+          }
+          break;
         }
-        continue;
-      }
-      if (any || all_pre) {
+        ix[l - 1][lane] = cand;
+        uint32_t any = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          yc[k] = yp[k] & TA[(size_t)cand * W + k];
+          any |= yc[k];
+        }
+        if (any) cne[l][lane] += 1ull;
+        if (!(any || all_pre)) break;
         // extended: its children are the sorted indices (idx(cand), G-h+l]
         const int kids = P.G - h + l - w.act[cand];
-#pragma unroll
-        for (int d = 4; d <= kMaxH; ++d)
-          if (d == l + 1) vis[d] += (unsigned long long)kids;
+        cvis[l + 1][lane] += (unsigned long long)kids;
+        if (l == h - 1) {
+          // the leaf depth is scored from the ring
+          push = any != 0;
+          break;
+        }
         ix[l][lane] = cand;
         level = l + 1;
 #pragma unroll
         for (int k = 0; k < W; ++k) yp[k] = yc[k];
+      } while (false);
+      // every lane of the wave is active again here
+      const unsigned long long bal = __ballot(push);
+      if (bal) {
+        if (push) {
+          const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          const int pos = (qt + rank) & (kDeepQ - 1);
+#pragma unroll
+          for (int k = 0; k < W; ++k) qy[(size_t)k * kDeepQ + pos] = yc[k];
+          for (int i = 0; i < h - 1; ++i) qix[i * kDeepQ + pos] = ix[i][lane];
+        }
+        qt += __popcll(bal);
+        if (qt - qh >= kWave) drain(kWave);
       }
     }
   }
+  if (qt > qh) drain(qt - qh);
 
   Slot sl = empty_slot();
   if (bs >= 0) {
@@ -196,14 +265,13 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   }
   block_best_to(&w.slots[(size_t)2 * kSlotsPerPhase + blockIdx.x], sl);
   // counters: one atomic per wave and depth
-#pragma unroll
-  for (int d = 3; d <= kMaxH; ++d) {
-    unsigned long long n = ne[d], v = vis[d];
+  for (int d = 3; d <= h; ++d) {
+    unsigned long long n = cne[d][lane] + (d == h ? ne_leaf : 0ull), v = cvis[d][lane];
     for (int o = 32; o > 0; o >>= 1) {
       n += __shfl_xor(n, o, 64);
       v += __shfl_xor(v, o, 64);
     }
-    if (lane == 0 && d <= h) {
+    if (lane == 0) {
       if (n) atomicAdd(&st->cnt.nonempty[d], n);
       if (d >= 4 && v) atomicAdd(&st->cnt.visited[d], v);
     }
@@ -234,6 +302,7 @@ hipError_t launch_deep_w(const Problem& P, const Work& w, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_dfs_deep(const Problem& P, const Work& w, hipStream_t s) {
+  if (!w.deepq || P.h < 5 || P.h > kMaxH) return hipErrorInvalidValue;
   switch (w.w64) {
 #define PDFS_CASE(n) \
   case n:            \

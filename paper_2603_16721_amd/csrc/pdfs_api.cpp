@@ -57,7 +57,7 @@ void release(pdfs_ctx* c) {
   void* ptrs[] = {c->Ts, c->Ns, c->perm, c->ncount, c->U, c->cols, c->act, c->flags, c->TA, c->NA,
                   c->A8, c->N8, c->pairs, c->work_pairs, c->seed_pairs, c->hist,
                   c->items, c->slots, c->tallies, c->st, c->recs, c->tri, c->tri_s,
-                  c->c_hist};
+                  c->c_hist, c->deepq};
   for (void* p : ptrs) dfree(c, p);
   if (c->h_st && c->own_h_st) (void)hipHostFree(c->h_st);
   for (auto& row : c->ev)
@@ -69,6 +69,12 @@ void release(pdfs_ctx* c) {
 }
 
 int words(int n) { return (n + 63) / 64; }
+
+// 32-bit words of the h >= 5 leaf-prefix rings: every wave of a full
+// persistent grid, rows of up to w64max 64-bit words
+static size_t deepq_words(int w64max) {
+  return (size_t)kWavesPerGrid * (size_t)(2 * w64max + kMaxH) * kDeepQ;
+}
 
 // Exhaustive mode makes every gene a row of the round (its row over the
 // uncovered samples may be empty), so the row-indexed buffers must hold G rows
@@ -117,6 +123,8 @@ int32_t ensure_workspace(pdfs_ctx* c, int h) {
   }
   if (h >= 3 && c->prune_mode == PDFS_PRUNE_BOUND && !c->work_pairs)
     CK(c, dalloc(c, &c->work_pairs, (size_t)c->pair_cap));
+  if (h >= 5 && !c->deepq)
+    CK(c, dalloc(c, &c->deepq, deepq_words(c->w64_max)));
   if (h == 2 && !c->N8) {
     size_t rows = (size_t)((c->nA_max + 127) / 128 * 128 + 128);
     CK(c, dalloc(c, &c->N8, rows * (size_t)unpacked_row_bytes(c->wn)));
@@ -139,6 +147,7 @@ Work make_work(pdfs_ctx* c, int w64, int target) {
   w.chunk = c->chunk_items; w.seed_n = c->seed_pairs_n;
   w.tri = c->tri; w.tri_s = c->tri_s; w.c_hist = c->c_hist;
   w.tri_cap = c->two_phase ? c->tri_cap : 0;
+  w.deepq = c->deepq;
   return w;
 }
 
@@ -543,6 +552,7 @@ size_t footprint_bytes(int G, int n_tumor, int n_normal, int nA_max, int h, int 
     b += pairs * 8 * (prune_mode == PDFS_PRUNE_BOUND ? 2 : 1) + items * sizeof(Item);
   }
   if (h == 2) b += rows * (size_t)unpacked_row_bytes((int)wn);
+  if (h >= 5) b += deepq_words(w64max) * 4;
   return b + ((size_t)1 << 20);
 }
 

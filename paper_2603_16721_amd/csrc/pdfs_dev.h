@@ -33,6 +33,7 @@ constexpr int kPersistBlocks = 1024;  // persistent grids: ~1.3 resident rounds 
 constexpr int kBlock = 256;        // 4 waves per block
 constexpr int kWavesPerGrid = kPersistBlocks * (kBlock / kWave);
 constexpr int kSlotsPerPhase = kPersistBlocks;   // one argmax slot per block
+constexpr int kDeepQ = 128;   // leaf-prefix ring entries per wave (h >= 5)
 constexpr int kSlotPhases = 3;     // pair kernel / seed DFS / main DFS
 constexpr int kSeedPairs = 256;    // bound mode: pairs expanded first to set the incumbent
 constexpr int kSeedCap = 1024;     // seed list capacity (ties at the threshold)
@@ -173,6 +174,9 @@ struct Work {
   unsigned long long* tri_s;
   uint32_t* c_hist;
   unsigned long long tri_cap;   // 0: count only
+  // h >= 5: one leaf-prefix ring of kDeepQ entries per wave of the deep walk
+  // ([tumour word][entry] intersections, then [depth][entry] indices)
+  uint32_t* deepq;
 };
 
 // ---------------------------------------------------------------- launchers

@@ -68,6 +68,7 @@ struct pdfs_ctx {
   unsigned long long* tri = nullptr;
   unsigned long long* tri_s = nullptr;
   uint32_t* c_hist = nullptr;
+  uint32_t* deepq = nullptr;   // h >= 5 leaf-prefix rings
   unsigned long long tri_cap = 0;
   bool two_phase = false;              // this run uses the two-phase path
   pdfs::Slot* slots = nullptr;

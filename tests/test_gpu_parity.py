@@ -240,6 +240,19 @@ def test_workload_h4_G20000_empty_round1_counters(pdfs):
     _counters_equal(stats, g, 4)
 
 
+@pytest.mark.parametrize("key", ["h5_G5000_empty_round1", "h6_G5000_empty_round1"])
+def test_workload_h3_G5000_deeper_round1(pdfs, key):
+    """Full-size cohort (G=5000, 1000 / 400 samples) at h = 5 and 6: the
+    first greedy round of the deep walk and its exact per-depth counts."""
+    I = synth.workload_h3_g5000()
+    T, N = I.packed()
+    g = _golden(key)
+    with pdfs.Solver(T, N, I.n_tumor, I.n_normal, "empty") as s:
+        got, stats, _ = s.wsc(g["h"], 1, 10, max_rounds=1)
+    _same_rounds(got, g["rounds"])
+    _counters_equal(stats, g, g["h"])
+
+
 def test_two_phase_depth4_medium(pdfs):
     """h = 4, empty-only walk with more active genes than the long-stream
     threshold (384 candidates): the round lists long-stream depth-3
