@@ -17,9 +17,10 @@
 // streams the leaf candidates c in (min last index, amax_h) through scalar
 // row loads, each lane masking the c at or below its own last index -- the
 // candidate row is loaded once per wave instead of once per lane.  Leaves
-// with TP >= 1 are scored S = p*TP + q*(N_n - FP) and compared with the
-// lane's best under (S desc, tuple asc); the normal join of a prefix is
-// formed only once one of its leaves can reach the lane's best (FP = 0).
+// whose TP reaches the lane's threshold (the least TP that can still replace
+// its best, ties included when the prefix precedes the best's) are scored
+// S = p*TP + q*(N_n - FP) and compared under (S desc, tuple asc); the normal
+// join of a prefix is formed at its first such leaf.
 //
 // Counters: non-empty prefixes per depth, and for every extended depth-l
 // prefix the depth-(l+1) visits of Alg. 2's loop bounds (sorted indices in
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   int bidx[kMaxH];
 #pragma unroll
   for (int i = 0; i < kMaxH; ++i) bidx[i] = 0;
-  unsigned long long ne_leaf = 0;
+  unsigned long long ne_w = 0;   // non-empty leaves (wave-uniform)
 
   // The wave takes `take` (1..64) queued prefixes, one per lane, and scores
   // their leaves.  Called with every lane of the wave active.
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
 #pragma unroll
     for (int k = 0; k < W; ++k) y[k] = v ? qy[(size_t)k * kDeepQ + e] : 0u;
     int pix[kMaxH];
-    int last = 0x7fffffff;
+    int last = 0x7fffffff;   // idle lanes mask every candidate
 #pragma unroll
     for (int i = 0; i < kMaxH; ++i) {
       pix[i] = (v && i < h - 1) ? qix[i * kDeepQ + e] : 0;
@@ -104,50 +105,98 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
     for (int o = 32; o > 0; o >>= 1) lo = min(lo, __shfl_xor(lo, o, 64));
     lo = uniform(lo);
     const int hi = s_amax[h];
+    // leaves of this prefix win a tie against the lane's best exactly when
+    // the prefix precedes the best's first h-1 indices
+    auto prefix_first = [&]() {
+      int cmp = 0;
+#pragma unroll
+      for (int i = 0; i < kMaxH - 1; ++i)
+        if (cmp == 0 && i < h - 1) cmp = pix[i] < bidx[i] ? -1 : (pix[i] > bidx[i] ? 1 : 0);
+      return cmp < 0;
+    };
+    int thr = min_tp_for(P, bs, bs < 0 || prefix_first());
     bool zr = false;
     uint32_t z[kMaxWN32];
 #pragma unroll
     for (int k = 0; k < kMaxWN32; ++k) z[k] = 0u;
-    for (int c = lo; c < hi; ++c) {
-      const int tp = popc_and<W>(y, TAc + (size_t)c * W);
-      if (!(v && c > last && tp > 0)) continue;
-      ++ne_leaf;
-      if (P.p * tp + qN < bs) continue;   // cannot reach the lane's best
+    // leaves of candidate d in lanes m (TP >= thr): score, compare, update
+    auto offer = [&](int d, int tp, unsigned long long m) {
+      if (!((m >> lane) & 1ull)) return;
       if (!zr) {
 #pragma unroll
         for (int k = 0; k < kMaxWN32; ++k) z[k] = lit ? 0u : ~0u;
 #pragma unroll
-        for (int d = 0; d < kMaxH; ++d) {
-          if (d < h - 1) {
+        for (int i = 0; i < kMaxH - 1; ++i) {
+          if (i < h - 1) {
 #pragma unroll
             for (int k = 0; k < kMaxWN32; ++k)
-              z[k] = nrm_join(z[k], NA[(size_t)pix[d] * kMaxWN32 + k], lit);
+              z[k] = nrm_join(z[k], NA[(size_t)pix[i] * kMaxWN32 + k], lit);
           }
         }
         zr = true;
       }
-      const int fp = leaf_fp(z, NAc + (size_t)c * kMaxWN32, lit);
-      const int s = P.p * tp + P.q * (P.n_normal - fp);
-      bool take_it = s > bs;
-      if (s == bs) {
+      const int fp = leaf_fp(z, NAc + (size_t)d * kMaxWN32, lit);
+      const int sc = P.p * tp + P.q * (P.n_normal - fp);
+      bool take_it = sc > bs;
+      if (sc == bs) {
         // equal score: the smaller tuple (lexicographic, sorted indices)
         int cmp = 0;
 #pragma unroll
         for (int i = 0; i < kMaxH; ++i) {
           if (cmp == 0 && i < h) {
-            const int x = i < h - 1 ? pix[i] : c;
+            const int x = i < h - 1 ? pix[i] : d;
             cmp = x < bidx[i] ? -1 : (x > bidx[i] ? 1 : 0);
           }
         }
         take_it = cmp < 0;
       }
       if (take_it) {
-        bs = s;
+        bs = sc;
         btp = tp;
         bfp = fp;
 #pragma unroll
-        for (int i = 0; i < kMaxH; ++i) bidx[i] = i < h - 1 ? pix[i] : (i == h - 1 ? c : 0);
+        for (int i = 0; i < kMaxH; ++i) bidx[i] = i < h - 1 ? pix[i] : (i == h - 1 ? d : 0);
       }
+      // the best now comes from this prefix (or precedes it): later leaves
+      // of the prefix lose ties
+      thr = min_tp_for(P, bs, bs < 0 || prefix_first());
+    };
+    auto step = [&](int d, const uint32_t (&row)[W]) {
+      const int tp = popc_and_r<W>(y, row);
+      const unsigned long long dm = __ballot(d > last);
+      ne_w += (unsigned long long)__popcll(__ballot(tp > 0) & dm);
+      const unsigned long long m = __ballot(tp >= thr) & dm;
+      if (m) offer(d, tp, m);
+    };
+    if (lo >= hi) return;
+    // candidates stream through two register buffers of KR rows each, the
+    // next group in flight while the current one is tested; TA holds at
+    // least 128 rows past the last active one, so groups are read unclamped
+    // and rows at or past hi are skipped
+    constexpr int KR = W <= 4 ? 4 : (W <= 16 ? 2 : 1);
+    int d = lo;
+    auto group = [&](const uint32_t (&r)[KR][W]) {
+#pragma unroll
+      for (int j = 0; j < KR; ++j)
+        if (d + j < hi) step(d + j, r[j]);
+      d += KR;
+    };
+    cu32* ptr = TAc + (size_t)d * W;
+    uint32_t ra[KR][W], rb[KR][W];
+    load_group<W, KR>(ra, ptr);
+    for (;;) {
+      cu32* pn = ptr + KR * W;
+      group_arrived<W, KR>(pn, ra);
+      load_group<W, KR>(rb, pn);
+      group(ra);
+      if (d >= hi) break;
+      ptr = pn;
+      pn = ptr + KR * W;
+      group_arrived<W, KR>(pn, rb);
+      load_group<W, KR>(ra, pn);
+      group(rb);
+      if (d >= hi) break;
+      ptr = pn;
     }
   };
 
@@ -266,7 +315,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   block_best_to(&w.slots[(size_t)2 * kSlotsPerPhase + blockIdx.x], sl);
   // counters: one atomic per wave and depth
   for (int d = 3; d <= h; ++d) {
-    unsigned long long n = cne[d][lane] + (d == h ? ne_leaf : 0ull), v = cvis[d][lane];
+    unsigned long long n = cne[d][lane] + (d == h && lane == 0 ? ne_w : 0ull), v = cvis[d][lane];
     for (int o = 32; o > 0; o >>= 1) {
       n += __shfl_xor(n, o, 64);
       v += __shfl_xor(v, o, 64);
