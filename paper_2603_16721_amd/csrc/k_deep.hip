@@ -1,33 +1,33 @@
 // Depth-first expansion for h = 5..9 (Alg. 2 depths 3..h, Sec. III-C).
 //
-// Work unit as for h <= 4: 64 non-empty pairs (one per lane) x a range of
-// depth-3 candidates.  Each lane walks its pair's subtree over depths
-// 3..h-1 in Alg. 2's order with an explicit stack: the candidate index of
-// every depth sits in LDS (one column per lane), the running intersection of
-// the parent of the depth being enumerated in VGPRs.  A candidate's
-// intersection is the parent's AND its row; a non-empty one (any one in
-// exhaustive mode) becomes the parent of the next depth, and on the way back
-// up the parent of the shallower depth is rebuilt from the stacked indices
-// (y2 AND the rows of depths 3..l-2), so only one intersection per lane is
-// ever held.
+// Every depth is expanded wave-wide, as the h <= 4 depth-4 loop does: a wave
+// holds 64 prefixes of one depth (one per lane) and streams the candidate
+// rows of the next depth through scalar loads, each lane masking the
+// candidates at or below its own last index; the candidate row is loaded
+// once per wave instead of once per lane, and no lane waits for another's
+// subtree.  Depth 3 comes from the work items (64 pairs x a range of
+// depth-3 candidates); a prefix of depth l (3 <= l < h) that is extended --
+// non-empty, or any in exhaustive mode -- goes into the wave's ring for
+// depth l in device memory ([word][entry] intersections, [depth][entry]
+// indices), and 64 entries of that ring make the next depth-(l+1) expansion.
+// When a ring holds 64 or more entries the expansion filling it is
+// suspended (its intersections, indices and position saved in the wave's
+// frame for that depth) and the deeper level runs first; so each ring stays
+// below 128 entries and at most one suspended expansion exists per depth.
+// Once the items are exhausted the rings are flushed shallowest first with
+// partial batches.
 //
-// The leaf depth is not walked per lane.  A non-empty depth-(h-1) prefix
-// (its intersection and indices) goes into a ring of the wave in device
-// memory; once 64 are queued the whole wave takes them, one per lane, and
-// streams the leaf candidates c in (min last index, amax_h) through scalar
-// row loads, each lane masking the c at or below its own last index -- the
-// candidate row is loaded once per wave instead of once per lane.  Leaves
-// whose TP reaches the lane's threshold (the least TP that can still replace
-// its best, ties included when the prefix precedes the best's) are scored
-// S = p*TP + q*(N_n - FP) and compared under (S desc, tuple asc); the normal
-// join of a prefix is formed at its first such leaf.
+// Leaves (depth h) whose TP reaches the lane's threshold (the least TP that
+// can still replace its best, ties included when the prefix precedes the
+// best's) are scored S = p*TP + q*(N_n - FP) and compared under (S desc,
+// tuple asc); the normal join of a prefix is formed at its first such leaf.
 //
 // Counters: non-empty prefixes per depth, and for every extended depth-l
 // prefix the depth-(l+1) visits of Alg. 2's loop bounds (sorted indices in
-// (idx(g_l), G-h+l]), added to the round's counters by one atomic per wave
-// and depth.  The depth-2 and depth-3 visit counts come from the pair
-// kernel, as for h <= 4.  Bound pruning is not applied at these depths; the
-// answers are the same (the bound is an exact pruning rule).
+// (idx(g_l), G-h+l]), per wave in LDS, then one atomic per wave and depth.
+// The depth-2 and depth-3 visit counts come from the pair kernel, as for
+// h <= 4.  Bound pruning is not applied at these depths; the answers are the
+// same (the bound is an exact pruning rule).
 #include "dfs_core.h"
 #include "pdfs_dev.h"
 #include "slot_reduce.h"
@@ -36,23 +36,30 @@ namespace pdfs {
 
 namespace {
 
+constexpr int kLv = kMaxH - 3;   // rings of depths 3..kMaxH-1, frames of depths 3..kMaxH-1
+
 template <int W64>
 __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   constexpr int W = 2 * W64;
-  __shared__ int stk[kBlock / kWave][kMaxH][kWave];   // candidate index per depth, per lane
+  constexpr int KR = W <= 4 ? 4 : (W <= 16 ? 2 : 1);
+  constexpr int kNone = 0x7fffffff;   // "last index" of an idle lane: masks every candidate
+  constexpr int kWib = kBlock / kWave;
   __shared__ int s_amax[kMaxH + 1];
-  // per-lane counters (own column, no atomics): [0] non-empty, [1] visited
-  __shared__ unsigned long long s_cnt[kBlock / kWave][2][kMaxH + 1][kWave];
+  __shared__ unsigned long long s_cnt[kWib][2][kMaxH + 1];   // [0] non-empty, [1] visited
+  __shared__ int s_q[kWib][2][kLv];   // per ring: entries taken, entries queued
+  __shared__ int s_f[kWib][2][kLv];   // per suspended frame: next candidate, end
   RoundState* st = w.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   if (threadIdx.x <= kMaxH) s_amax[threadIdx.x] = st->amax[threadIdx.x];
-  int (*ix)[kWave] = stk[wib];
-  unsigned long long (*cne)[kWave] = s_cnt[wib][0];
-  unsigned long long (*cvis)[kWave] = s_cnt[wib][1];
-  for (int d = 0; d <= kMaxH; ++d) cne[d][lane] = cvis[d][lane] = 0ull;
+  if (lane <= kMaxH) s_cnt[wib][0][lane] = s_cnt[wib][1][lane] = 0ull;
+  if (lane < kLv) s_q[wib][0][lane] = s_q[wib][1][lane] = 0;
   __syncthreads();
+  unsigned long long* cne = s_cnt[wib][0];
+  unsigned long long* cvis = s_cnt[wib][1];
+  int* q_taken = s_q[wib][0];
+  int* q_queued = s_q[wib][1];
   const int h = P.h;
   const bool all_pre = P.mode == kPruneNone;
   const bool lit = P.tn_literal != 0;
@@ -68,43 +75,157 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   cu32* NAc = (cu32*)w.NA;
   const int qN = P.q * P.n_normal;
 
-  // this wave's leaf-prefix ring: [W][kDeepQ] intersections, [kMaxH][kDeepQ]
-  // indices; qh / qt count entries taken / queued (wave-uniform)
-  uint32_t* __restrict__ qy =
-      w.deepq + (size_t)(blockIdx.x * (kBlock / kWave) + wib) * (size_t)(W + kMaxH) * kDeepQ;
-  int* __restrict__ qix = reinterpret_cast<int*>(qy + (size_t)W * kDeepQ);
-  int qh = 0, qt = 0;
+  // this wave's rings and frames
+  constexpr size_t kRingWords = (size_t)(W + kMaxH) * kDeepQ;
+  constexpr size_t kFrameWords = (size_t)(W + kMaxH + 1) * kWave;
+  uint32_t* __restrict__ area =
+      w.deepq + (size_t)(blockIdx.x * kWib + wib) * (kLv * (kRingWords + kFrameWords));
+  auto ring_y = [&](int l) { return area + (size_t)(l - 3) * kRingWords; };
+  auto ring_ix = [&](int l) {
+    return reinterpret_cast<int*>(area + (size_t)(l - 3) * kRingWords + (size_t)W * kDeepQ);
+  };
+  auto frame = [&](int l) { return area + kLv * kRingWords + (size_t)(l - 3) * kFrameWords; };
+  auto queued = [&](int l) { return uniform(q_queued[l - 3]) - uniform(q_taken[l - 3]); };
 
   int bs = -1, btp = 0, bfp = 0;
   int bidx[kMaxH];
 #pragma unroll
   for (int i = 0; i < kMaxH; ++i) bidx[i] = 0;
-  unsigned long long ne_w = 0;   // non-empty leaves (wave-uniform)
 
-  // The wave takes `take` (1..64) queued prefixes, one per lane, and scores
-  // their leaves.  Called with every lane of the wave active.
-  auto drain = [&](int take) {
-    // the entries were written by other lanes of this wave
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const bool v = lane < take;
-    const int e = (qh + lane) & (kDeepQ - 1);
-    uint32_t y[W];
+  // the expansion in registers: depth L, the lanes' prefixes of depth L-1
+  // (intersection y, indices pix, last index), candidates d..hi-1
+  int L = 3, d = 0, hi = 0;
+  uint32_t y[W];
+  int pix[kMaxH];
+  int last = kNone;
 #pragma unroll
-    for (int k = 0; k < W; ++k) y[k] = v ? qy[(size_t)k * kDeepQ + e] : 0u;
-    int pix[kMaxH];
-    int last = 0x7fffffff;   // idle lanes mask every candidate
+  for (int k = 0; k < W; ++k) y[k] = 0u;
+#pragma unroll
+  for (int i = 0; i < kMaxH; ++i) pix[i] = 0;
+
+  auto wave_first = [&](int x) {   // smallest x over the wave
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
+    return uniform(x);
+  };
+  // 1..64 entries of the depth-l ring into the registers (depth l+1 next)
+  auto take = [&](int l, int n) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // written by other lanes
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int qh = uniform(q_taken[l - 3]);
+    const bool v = lane < n;
+    const int e = (qh + lane) & (kDeepQ - 1);
+    const uint32_t* __restrict__ ry = ring_y(l);
+    const int* __restrict__ ri = ring_ix(l);
+#pragma unroll
+    for (int k = 0; k < W; ++k) y[k] = v ? ry[(size_t)k * kDeepQ + e] : 0u;
+    last = kNone;
 #pragma unroll
     for (int i = 0; i < kMaxH; ++i) {
-      pix[i] = (v && i < h - 1) ? qix[i * kDeepQ + e] : 0;
-      if (v && i == h - 2) last = pix[i];
+      pix[i] = (v && i < l) ? ri[i * kDeepQ + e] : 0;
+      if (v && i == l - 1) last = pix[i];
     }
-    qh += take;
-    int lo = last == 0x7fffffff ? last : last + 1;
+    q_taken[l - 3] = qh + n;
+    L = l + 1;
+    d = wave_first(last == kNone ? kNone : last + 1);
+    hi = s_amax[L];
+  };
+  auto save = [&]() {   // the registers into the frame of depth L
+    uint32_t* f = frame(L);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) lo = min(lo, __shfl_xor(lo, o, 64));
-    lo = uniform(lo);
-    const int hi = s_amax[h];
+    for (int k = 0; k < W; ++k) f[(size_t)k * kWave + lane] = y[k];
+#pragma unroll
+    for (int i = 0; i < kMaxH; ++i) f[(size_t)(W + i) * kWave + lane] = (uint32_t)pix[i];
+    f[(size_t)(W + kMaxH) * kWave + lane] = (uint32_t)last;
+    s_f[wib][0][L - 3] = d;
+    s_f[wib][1][L - 3] = hi;
+  };
+  auto restore = [&]() {   // the frame of depth L into the registers
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint32_t* f = frame(L);
+#pragma unroll
+    for (int k = 0; k < W; ++k) y[k] = f[(size_t)k * kWave + lane];
+#pragma unroll
+    for (int i = 0; i < kMaxH; ++i) pix[i] = (int)f[(size_t)(W + i) * kWave + lane];
+    last = (int)f[(size_t)(W + kMaxH) * kWave + lane];
+    d = uniform(s_f[wib][0][L - 3]);
+    hi = uniform(s_f[wib][1][L - 3]);
+  };
+
+  // Inner depth L < h: candidates from d on until hi or until the depth-L
+  // ring holds 64 entries.  Rows stream through two groups of KR rows, the
+  // next in flight while the current one is tested (TA holds at least 128
+  // rows past the last active one, so groups are read unclamped).
+  auto run_inner = [&]() {
+    const int l = L;
+    uint32_t* __restrict__ ry = ring_y(l);
+    int* __restrict__ ri = ring_ix(l);
+    bool full = false;
+    auto step = [&](int dd, const uint32_t (&row)[W]) {
+      uint32_t yc[W];
+      uint32_t any = 0;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        yc[k] = y[k] & row[k];
+        any |= yc[k];
+      }
+      const unsigned long long mk = __ballot(dd > last);
+      const unsigned long long mn = __ballot(any != 0) & mk;
+      const unsigned long long mx = all_pre ? mk : mn;   // extended
+      if (lane == 0) {
+        cne[l] += (unsigned long long)__popcll(mn);
+        // children of an extended prefix: the sorted indices (idx(dd), G-h+l]
+        cvis[l + 1] += (unsigned long long)__popcll(mx) *
+                       (unsigned long long)(P.G - h + l - w.act[dd]);
+      }
+      if (mx) {
+        const int qt = uniform(q_queued[l - 3]);
+        if ((mx >> lane) & 1ull) {
+          const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(mx >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mx, 0u));
+          const int pos = (qt + rank) & (kDeepQ - 1);
+#pragma unroll
+          for (int k = 0; k < W; ++k) ry[(size_t)k * kDeepQ + pos] = yc[k];
+          for (int i = 0; i < l - 1; ++i) ri[i * kDeepQ + pos] = pix[i];
+          ri[(l - 1) * kDeepQ + pos] = dd;
+        }
+        const int qt2 = qt + __popcll(mx);
+        q_queued[l - 3] = qt2;
+        full = qt2 - uniform(q_taken[l - 3]) >= kWave;
+      }
+    };
+    auto group = [&](const uint32_t (&r)[KR][W]) {
+#pragma unroll
+      for (int j = 0; j < KR; ++j)
+        if (d < hi && !full) {
+          step(d, r[j]);
+          ++d;
+        }
+    };
+    if (d >= hi) return;
+    cu32* ptr = TAc + (size_t)d * W;
+    uint32_t ra[KR][W], rb[KR][W];
+    load_group<W, KR>(ra, ptr);
+    for (;;) {
+      cu32* pn = ptr + KR * W;
+      group_arrived<W, KR>(pn, ra);
+      load_group<W, KR>(rb, pn);
+      group(ra);
+      if (d >= hi || full) break;
+      ptr = pn;
+      pn = ptr + KR * W;
+      group_arrived<W, KR>(pn, rb);
+      load_group<W, KR>(ra, pn);
+      group(rb);
+      if (d >= hi || full) break;
+      ptr = pn;
+    }
+  };
+
+  // Leaf depth: every candidate from d to hi, scored against the lane's best.
+  auto run_leaves = [&]() {
+    unsigned long long ne = 0;
     // leaves of this prefix win a tie against the lane's best exactly when
     // the prefix precedes the best's first h-1 indices
     auto prefix_first = [&]() {
@@ -119,8 +240,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
     uint32_t z[kMaxWN32];
 #pragma unroll
     for (int k = 0; k < kMaxWN32; ++k) z[k] = 0u;
-    // leaves of candidate d in lanes m (TP >= thr): score, compare, update
-    auto offer = [&](int d, int tp, unsigned long long m) {
+    auto offer = [&](int dd, int tp, unsigned long long m) {
       if (!((m >> lane) & 1ull)) return;
       if (!zr) {
 #pragma unroll
@@ -135,7 +255,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
         }
         zr = true;
       }
-      const int fp = leaf_fp(z, NAc + (size_t)d * kMaxWN32, lit);
+      const int fp = leaf_fp(z, NAc + (size_t)dd * kMaxWN32, lit);
       const int sc = P.p * tp + P.q * (P.n_normal - fp);
       bool take_it = sc > bs;
       if (sc == bs) {
@@ -144,7 +264,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
 #pragma unroll
         for (int i = 0; i < kMaxH; ++i) {
           if (cmp == 0 && i < h) {
-            const int x = i < h - 1 ? pix[i] : d;
+            const int x = i < h - 1 ? pix[i] : dd;
             cmp = x < bidx[i] ? -1 : (x > bidx[i] ? 1 : 0);
           }
         }
@@ -155,154 +275,143 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
         btp = tp;
         bfp = fp;
 #pragma unroll
-        for (int i = 0; i < kMaxH; ++i) bidx[i] = i < h - 1 ? pix[i] : (i == h - 1 ? d : 0);
+        for (int i = 0; i < kMaxH; ++i) bidx[i] = i < h - 1 ? pix[i] : (i == h - 1 ? dd : 0);
       }
       // the best now comes from this prefix (or precedes it): later leaves
       // of the prefix lose ties
       thr = min_tp_for(P, bs, bs < 0 || prefix_first());
     };
-    auto step = [&](int d, const uint32_t (&row)[W]) {
+    auto step = [&](int dd, const uint32_t (&row)[W]) {
       const int tp = popc_and_r<W>(y, row);
-      const unsigned long long dm = __ballot(d > last);
-      ne_w += (unsigned long long)__popcll(__ballot(tp > 0) & dm);
+      const unsigned long long dm = __ballot(dd > last);
+      ne += (unsigned long long)__popcll(__ballot(tp > 0) & dm);
       const unsigned long long m = __ballot(tp >= thr) & dm;
-      if (m) offer(d, tp, m);
+      if (m) offer(dd, tp, m);
     };
-    if (lo >= hi) return;
-    // candidates stream through two register buffers of KR rows each, the
-    // next group in flight while the current one is tested; TA holds at
-    // least 128 rows past the last active one, so groups are read unclamped
-    // and rows at or past hi are skipped
-    constexpr int KR = W <= 4 ? 4 : (W <= 16 ? 2 : 1);
-    int d = lo;
     auto group = [&](const uint32_t (&r)[KR][W]) {
 #pragma unroll
       for (int j = 0; j < KR; ++j)
         if (d + j < hi) step(d + j, r[j]);
       d += KR;
     };
-    cu32* ptr = TAc + (size_t)d * W;
-    uint32_t ra[KR][W], rb[KR][W];
-    load_group<W, KR>(ra, ptr);
-    for (;;) {
-      cu32* pn = ptr + KR * W;
-      group_arrived<W, KR>(pn, ra);
-      load_group<W, KR>(rb, pn);
-      group(ra);
-      if (d >= hi) break;
-      ptr = pn;
-      pn = ptr + KR * W;
-      group_arrived<W, KR>(pn, rb);
-      load_group<W, KR>(ra, pn);
-      group(rb);
-      if (d >= hi) break;
-      ptr = pn;
-    }
-  };
-
-  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
-  const uint32_t gw = blockIdx.x * (kBlock / kWave) + wib;
-  bool first = true;
-  for (;;) {
-    uint32_t it = nitems;
-    if (first) {
-      it = gw;
-      first = false;
-    } else if (lane == 0) {
-      const unsigned long long cur =
-          __hip_atomic_load(&st->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (cur + nwaves < nitems)
-        it = (uint32_t)(nwaves + atomicAdd(&st->cursor, 1ull));
-    }
-    it = (uint32_t)uniform((int)it);
-    if (it >= nitems) break;
-    const int c_lo = uniform((int)w.items[it].c_lo);
-    const int c_hi = uniform((int)w.items[it].c_hi);
-    const uint32_t batch = (uint32_t)uniform((int)w.items[it].batch);
-    const unsigned long long pi = (unsigned long long)batch * kPairBatch + lane;
-    bool valid = pi < npairs;
-    const unsigned long long e = valid ? plist[pi] : 0ull;
-    const int a = (int)(e & 0xffff);
-    const int b = (int)((e >> 16) & 0xffff);
-    valid = valid && a < b && b < nA_all;   // list entries always satisfy this
-    const int lo3 = c_lo > b + 1 ? c_lo : b + 1;
-    bool live = valid && lo3 < c_hi;
-    if (!__any(live)) continue;
-    const int ra = valid ? a : 0, rb = valid ? b : 0;   // in-range rows for idle lanes
-    uint32_t y2[W], yp[W], yc[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      y2[k] = TA[(size_t)ra * W + k] & TA[(size_t)rb * W + k];
-      yp[k] = y2[k];
-      yc[k] = 0u;
-    }
-    ix[0][lane] = a;
-    ix[1][lane] = b;
-    ix[2][lane] = lo3 - 1;
-    int level = 3;   // the depth whose candidates the lane enumerates
-    while (__any(live)) {
-      bool push = false;   // a non-empty depth-(h-1) prefix in yc / ix
-      do {
-        if (!live) break;
-        const int l = level;
-        const int cand = ix[l - 1][lane] + 1;
-        const int hi = l == 3 ? c_hi : s_amax[l];
-        if (cand >= hi) {
-          // this depth is exhausted: back to depth l-1, whose candidates'
-          // parent is the intersection of depths 1..l-2
-          if (l == 3) {
-            live = false;
-            break;
-          }
-          level = l - 1;
-#pragma unroll
-          for (int k = 0; k < W; ++k) yp[k] = y2[k];
-          for (int d = 3; d <= l - 2; ++d) {
-            const int r = ix[d - 1][lane];
-#pragma unroll
-            for (int k = 0; k < W; ++k) yp[k] &= TA[(size_t)r * W + k];
-          }
-          break;
-        }
-        ix[l - 1][lane] = cand;
-        uint32_t any = 0;
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-          yc[k] = yp[k] & TA[(size_t)cand * W + k];
-          any |= yc[k];
-        }
-        if (any) cne[l][lane] += 1ull;
-        if (!(any || all_pre)) break;
-        // extended: its children are the sorted indices (idx(cand), G-h+l]
-        const int kids = P.G - h + l - w.act[cand];
-        cvis[l + 1][lane] += (unsigned long long)kids;
-        if (l == h - 1) {
-          // the leaf depth is scored from the ring
-          push = any != 0;
-          break;
-        }
-        ix[l][lane] = cand;
-        level = l + 1;
-#pragma unroll
-        for (int k = 0; k < W; ++k) yp[k] = yc[k];
-      } while (false);
-      // every lane of the wave is active again here
-      const unsigned long long bal = __ballot(push);
-      if (bal) {
-        if (push) {
-          const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-              (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-          const int pos = (qt + rank) & (kDeepQ - 1);
-#pragma unroll
-          for (int k = 0; k < W; ++k) qy[(size_t)k * kDeepQ + pos] = yc[k];
-          for (int i = 0; i < h - 1; ++i) qix[i * kDeepQ + pos] = ix[i][lane];
-        }
-        qt += __popcll(bal);
-        if (qt - qh >= kWave) drain(kWave);
+    if (d < hi) {
+      cu32* ptr = TAc + (size_t)d * W;
+      uint32_t ra[KR][W], rb[KR][W];
+      load_group<W, KR>(ra, ptr);
+      for (;;) {
+        cu32* pn = ptr + KR * W;
+        group_arrived<W, KR>(pn, ra);
+        load_group<W, KR>(rb, pn);
+        group(ra);
+        if (d >= hi) break;
+        ptr = pn;
+        pn = ptr + KR * W;
+        group_arrived<W, KR>(pn, rb);
+        load_group<W, KR>(ra, pn);
+        group(rb);
+        if (d >= hi) break;
+        ptr = pn;
       }
     }
+    if (lane == 0) cne[h] += ne;
+  };
+
+  const uint32_t nwaves = gridDim.x * kWib;
+  const uint32_t gw = blockIdx.x * kWib + wib;
+  bool first = true, items_done = false, have = false;
+  uint32_t susp = 0;   // bit l: the expansion of depth l is suspended in its frame
+  int idle = 0;        // scheduling passes since the last expansion ran
+  for (;;) {
+    if (!have) {
+      // every pass takes an item, readies an expansion or moves one depth
+      // up: a long run of passes without the first two is a fault
+      if (++idle > 4 * kMaxH + 16) {
+        if (lane == 0) atomicOr(&st->overflow, 4);
+        break;
+      }
+      if (L == 3) {
+        if (!items_done) {
+          // the next work item: 64 pairs x depth-3 candidates [c_lo, c_hi)
+          uint32_t it = nitems;
+          if (first) {
+            it = gw;
+            first = false;
+          } else if (lane == 0) {
+            const unsigned long long cur =
+                __hip_atomic_load(&st->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cur + nwaves < nitems) it = (uint32_t)(nwaves + atomicAdd(&st->cursor, 1ull));
+          }
+          it = (uint32_t)uniform((int)it);
+          if (it >= nitems) {
+            items_done = true;
+          } else {
+            idle = 0;
+            const int c_lo = uniform((int)w.items[it].c_lo);
+            const int c_hi = uniform((int)w.items[it].c_hi);
+            const uint32_t batch = (uint32_t)uniform((int)w.items[it].batch);
+            const unsigned long long pi = (unsigned long long)batch * kPairBatch + lane;
+            bool valid = pi < npairs;
+            const unsigned long long e = valid ? plist[pi] : 0ull;
+            const int a = (int)(e & 0xffff);
+            const int b = (int)((e >> 16) & 0xffff);
+            valid = valid && a < b && b < nA_all;   // list entries always satisfy this
+            const int ra = valid ? a : 0, rb = valid ? b : 0;   // in-range rows for idle lanes
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+              y[k] = valid ? TA[(size_t)ra * W + k] & TA[(size_t)rb * W + k] : 0u;
+#pragma unroll
+            for (int i = 0; i < kMaxH; ++i) pix[i] = i == 0 ? ra : (i == 1 ? rb : 0);
+            last = valid ? b : kNone;
+            d = wave_first(valid ? (b + 1 > c_lo ? b + 1 : c_lo) : kNone);
+            hi = c_hi;
+            have = d < hi;
+          }
+        }
+        if (items_done) {
+          // flush: the shallowest ring that still holds entries
+          int l = 3;
+          while (l < h && queued(l) == 0) ++l;
+          if (l >= h) break;
+          const int n = queued(l);
+          take(l, n < kWave ? n : kWave);
+          have = true;
+        }
+        continue;
+      }
+      // depth L >= 4: a batch of the depth-(L-1) ring, the suspended parent
+      // expansion, or back up
+      const int n = queued(L - 1);
+      const bool parent = (susp >> (L - 1)) & 1u;
+      if (n >= kWave || (items_done && n > 0 && !parent)) {
+        take(L - 1, n < kWave ? n : kWave);
+        have = true;
+      } else if (parent) {
+        L = L - 1;
+        susp &= ~(1u << L);
+        restore();
+        have = true;
+      } else {
+        L = L - 1;
+      }
+      continue;
+    }
+    idle = 0;
+    if (L == h) {
+      run_leaves();
+      have = false;
+      continue;
+    }
+    run_inner();
+    have = false;
+    if (d < hi) {
+      // the depth-L ring is full: its batches first, this expansion later
+      save();
+      susp |= 1u << L;
+      L = L + 1;
+    } else if (queued(L) >= kWave) {
+      L = L + 1;
+    }
   }
-  if (qt > qh) drain(qt - qh);
 
   Slot sl = empty_slot();
   if (bs >= 0) {
@@ -314,15 +423,10 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   }
   block_best_to(&w.slots[(size_t)2 * kSlotsPerPhase + blockIdx.x], sl);
   // counters: one atomic per wave and depth
-  for (int d = 3; d <= h; ++d) {
-    unsigned long long n = cne[d][lane] + (d == h && lane == 0 ? ne_w : 0ull), v = cvis[d][lane];
-    for (int o = 32; o > 0; o >>= 1) {
-      n += __shfl_xor(n, o, 64);
-      v += __shfl_xor(v, o, 64);
-    }
-    if (lane == 0) {
-      if (n) atomicAdd(&st->cnt.nonempty[d], n);
-      if (d >= 4 && v) atomicAdd(&st->cnt.visited[d], v);
+  if (lane == 0) {
+    for (int l = 3; l <= h; ++l) {
+      if (cne[l]) atomicAdd(&st->cnt.nonempty[l], cne[l]);
+      if (l >= 4 && cvis[l]) atomicAdd(&st->cnt.visited[l], cvis[l]);
     }
   }
   for (int vb = blockIdx.x + gridDim.x; vb < kPersistBlocks; vb += gridDim.x)

@@ -70,10 +70,13 @@ void release(pdfs_ctx* c) {
 
 int words(int n) { return (n + 63) / 64; }
 
-// 32-bit words of the h >= 5 leaf-prefix rings: every wave of a full
-// persistent grid, rows of up to w64max 64-bit words
+// 32-bit words of the h >= 5 prefix rings and suspended-expansion frames:
+// every wave of a full persistent grid, one ring and one frame per depth
+// 3..kMaxH-1, rows of up to w64max 64-bit words
 static size_t deepq_words(int w64max) {
-  return (size_t)kWavesPerGrid * (size_t)(2 * w64max + kMaxH) * kDeepQ;
+  const size_t W = 2 * (size_t)w64max;
+  return (size_t)kWavesPerGrid * (kMaxH - 3) *
+         ((W + kMaxH) * kDeepQ + (W + kMaxH + 1) * kWave);
 }
 
 // Exhaustive mode makes every gene a row of the round (its row over the
@@ -398,6 +401,10 @@ int32_t run_poll(pdfs_ctx* c, bool wait, bool* ready, bool* done) {
   if (st.overflow & 2) {
     r.active = false;
     return fail(c, PDFS_ERR_DEVICE, "corrupt per-wave result slot or listed prefix");
+  }
+  if (st.overflow & 4) {
+    r.active = false;
+    return fail(c, PDFS_ERR_DEVICE, "deep walk scheduler made no progress");
   }
   if (st.overflow) {
     r.active = false;

@@ -33,7 +33,7 @@ constexpr int kPersistBlocks = 1024;  // persistent grids: ~1.3 resident rounds 
 constexpr int kBlock = 256;        // 4 waves per block
 constexpr int kWavesPerGrid = kPersistBlocks * (kBlock / kWave);
 constexpr int kSlotsPerPhase = kPersistBlocks;   // one argmax slot per block
-constexpr int kDeepQ = 128;   // leaf-prefix ring entries per wave (h >= 5)
+constexpr int kDeepQ = 128;   // entries per prefix ring of the h >= 5 walk
 constexpr int kSlotPhases = 3;     // pair kernel / seed DFS / main DFS
 constexpr int kSeedPairs = 256;    // bound mode: pairs expanded first to set the incumbent
 constexpr int kSeedCap = 1024;     // seed list capacity (ties at the threshold)
@@ -72,7 +72,8 @@ struct RoundState {
   unsigned long long incumbent;    // bound key: (S+1)<<32 | (~a & 0xffff)<<16 | (~b & 0xffff)
   unsigned long long n_seed;       // pairs selected for the seed phase
   int32_t seed_t;                  // seed threshold on the pair count
-  int32_t overflow;                // bit 0: a list hit its capacity; bit 1: corrupt slot
+  int32_t overflow;                // bit 0: a list hit its capacity; bit 1: corrupt slot;
+                                   // bit 2: the h >= 5 walk's scheduler stalled
   Counters cnt;                    // this round's counters
   // work the DFS kernels had to do (active candidates only)
   unsigned long long x_vis3, x_vis4, x_leaves, x_fp_leaves;
@@ -174,8 +175,9 @@ struct Work {
   unsigned long long* tri_s;
   uint32_t* c_hist;
   unsigned long long tri_cap;   // 0: count only
-  // h >= 5: one leaf-prefix ring of kDeepQ entries per wave of the deep walk
-  // ([tumour word][entry] intersections, then [depth][entry] indices)
+  // h >= 5: per wave of the deep walk and depth 3..kMaxH-1, a prefix ring of
+  // kDeepQ entries ([tumour word][entry] intersections, then [depth][entry]
+  // indices) and a frame for a suspended expansion ([word][lane])
   uint32_t* deepq;
 };
 
