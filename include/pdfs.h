@@ -181,9 +181,9 @@ int32_t pdfs_set_prune_mode(pdfs_ctx *ctx, int32_t prune_mode);
  * words, NULL = every tumour sample).  alpha = alpha_p / alpha_q with
  * alpha_q >= 1.  Returns PDFS_OK with *out filled, PDFS_NO_COMBO when no
  * subset has TP >= 1 (out->h = 0), or an error.  stats may be NULL; it is
- * overwritten.  h: 1..PDFS_MAX_H (h = 5..9 run a per-lane subtree walk
- * below the pair level, without the bound test at those depths; the
- * answers are the same in every prune mode). */
+ * overwritten.  h: 1..PDFS_MAX_H (h = 5..9 expand every depth below the
+ * pair level wave-wide through per-depth prefix rings, without the bound
+ * test at those depths; the answers are the same in every prune mode). */
 int32_t pdfs_best_combo(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alpha_q,
                         const uint64_t *uncovered, pdfs_combo *out, pdfs_stats *stats);
 

@@ -78,7 +78,7 @@ def test_wsc_tiny(pdfs, case, mode):
         _counters_equal(stats, exp.counters, h)
 
 
-# h = 5..9: the per-lane subtree walk (every mode; BOUND runs the same walk)
+# h = 5..9: the ring walk below the pair level (every mode; BOUND runs the same walk)
 DEEP = [
     # seed, G, n_tumor, n_normal, density, h, alpha
     (201, 40, 100, 30, 0.25, 5, (1, 10)),
