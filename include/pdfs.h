@@ -182,8 +182,8 @@ int32_t pdfs_set_prune_mode(pdfs_ctx *ctx, int32_t prune_mode);
  * alpha_q >= 1.  Returns PDFS_OK with *out filled, PDFS_NO_COMBO when no
  * subset has TP >= 1 (out->h = 0), or an error.  stats may be NULL; it is
  * overwritten.  h: 1..PDFS_MAX_H (h = 5..9 expand every depth below the
- * pair level wave-wide through per-depth prefix rings, without the bound
- * test at those depths; the answers are the same in every prune mode). */
+ * pair level wave-wide through per-depth prefix rings; the answers are the
+ * same in every prune mode). */
 int32_t pdfs_best_combo(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alpha_q,
                         const uint64_t *uncovered, pdfs_combo *out, pdfs_stats *stats);
 

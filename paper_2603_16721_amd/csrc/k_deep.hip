@@ -22,12 +22,15 @@
 // best's) are scored S = p*TP + q*(N_n - FP) and compared under (S desc,
 // tuple asc); the normal join of a prefix is formed at its first such leaf.
 //
-// Counters: non-empty prefixes per depth, and for every extended depth-l
-// prefix the depth-(l+1) visits of Alg. 2's loop bounds (sorted indices in
-// (idx(g_l), G-h+l]), per wave in LDS, then one atomic per wave and depth.
-// The depth-2 and depth-3 visit counts come from the pair kernel, as for
-// h <= 4.  Bound pruning is not applied at these depths; the answers are the
-// same (the bound is an exact pruning rule).
+// Bound mode: a prefix whose score bound p*TP + q*N_n cannot reach the
+// round's incumbent (or ties it with larger first two indices) is not
+// extended; leaves that become a lane's best raise the incumbent.
+//
+// Counters: non-empty prefixes per depth, bound-pruned prefixes per depth,
+// and for every extended depth-l prefix the depth-(l+1) visits of Alg. 2's
+// loop bounds (sorted indices in (idx(g_l), G-h+l]), per wave in LDS, then
+// one atomic per wave and depth.  The depth-2 and depth-3 visit counts come
+// from the pair kernel, as for h <= 4.
 #include "dfs_core.h"
 #include "pdfs_dev.h"
 #include "slot_reduce.h"
@@ -45,7 +48,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   constexpr int kNone = 0x7fffffff;   // "last index" of an idle lane: masks every candidate
   constexpr int kWib = kBlock / kWave;
   __shared__ int s_amax[kMaxH + 1];
-  __shared__ unsigned long long s_cnt[kWib][2][kMaxH + 1];   // [0] non-empty, [1] visited
+  __shared__ unsigned long long s_cnt[kWib][3][kMaxH + 1];   // non-empty, visited, bound-pruned
   __shared__ int s_q[kWib][2][kLv];   // per ring: entries taken, entries queued
   __shared__ int s_f[kWib][2][kLv];   // per suspended frame: next candidate, end
   RoundState* st = w.st;
@@ -53,15 +56,18 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   if (threadIdx.x <= kMaxH) s_amax[threadIdx.x] = st->amax[threadIdx.x];
-  if (lane <= kMaxH) s_cnt[wib][0][lane] = s_cnt[wib][1][lane] = 0ull;
+  if (lane <= kMaxH) s_cnt[wib][0][lane] = s_cnt[wib][1][lane] = s_cnt[wib][2][lane] = 0ull;
   if (lane < kLv) s_q[wib][0][lane] = s_q[wib][1][lane] = 0;
   __syncthreads();
   unsigned long long* cne = s_cnt[wib][0];
   unsigned long long* cvis = s_cnt[wib][1];
+  unsigned long long* cbp = s_cnt[wib][2];
   int* q_taken = s_q[wib][0];
   int* q_queued = s_q[wib][1];
   const int h = P.h;
   const bool all_pre = P.mode == kPruneNone;
+  const bool bound = P.mode == kPruneBound;
+  unsigned long long inc = 0;   // the round's incumbent key as last seen by this lane
   const bool lit = P.tn_literal != 0;
   const unsigned long long* __restrict__ plist = w.work_pairs;
   const unsigned long long npairs = st->n_work_pairs;
@@ -126,6 +132,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
       if (v && i == l - 1) last = pix[i];
     }
     q_taken[l - 3] = qh + n;
+    if (bound) inc = load_incumbent(st);
     L = l + 1;
     d = wave_first(last == kNone ? kNone : last + 1);
     hi = s_amax[L];
@@ -151,6 +158,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
     last = (int)f[(size_t)(W + kMaxH) * kWave + lane];
     d = uniform(s_f[wib][0][L - 3]);
     hi = uniform(s_f[wib][1][L - 3]);
+    if (bound) inc = load_incumbent(st);
   };
 
   // Inner depth L < h: candidates from d on until hi or until the depth-L
@@ -172,7 +180,18 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
       }
       const unsigned long long mk = __ballot(dd > last);
       const unsigned long long mn = __ballot(any != 0) & mk;
-      const unsigned long long mx = all_pre ? mk : mn;   // extended
+      unsigned long long mx = all_pre ? mk : mn;   // extended
+      if (bound && mx) {
+        int t = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) t += __popc(yc[k]);
+        const unsigned long long md =
+            __ballot(((mx >> lane) & 1ull) && dominated(P.p * t + qN, pix[0], pix[1], inc));
+        if (md) {
+          mx &= ~md;
+          if (lane == 0) cbp[l] += (unsigned long long)__popcll(md);
+        }
+      }
       if (lane == 0) {
         cne[l] += (unsigned long long)__popcll(mn);
         // children of an extended prefix: the sorted indices (idx(dd), G-h+l]
@@ -276,6 +295,13 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
         bfp = fp;
 #pragma unroll
         for (int i = 0; i < kMaxH; ++i) bidx[i] = i < h - 1 ? pix[i] : (i == h - 1 ? dd : 0);
+        if (bound) {
+          const unsigned long long key = leaf_key(sc, pix[0], pix[1]);
+          if (key > inc) {
+            const unsigned long long old = atomicMax(&st->incumbent, key);
+            inc = old > key ? old : key;
+          }
+        }
       }
       // the best now comes from this prefix (or precedes it): later leaves
       // of the prefix lose ties
@@ -362,6 +388,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
 #pragma unroll
             for (int i = 0; i < kMaxH; ++i) pix[i] = i == 0 ? ra : (i == 1 ? rb : 0);
             last = valid ? b : kNone;
+            if (bound) inc = load_incumbent(st);
             d = wave_first(valid ? (b + 1 > c_lo ? b + 1 : c_lo) : kNone);
             hi = c_hi;
             have = d < hi;
@@ -427,6 +454,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
     for (int l = 3; l <= h; ++l) {
       if (cne[l]) atomicAdd(&st->cnt.nonempty[l], cne[l]);
       if (l >= 4 && cvis[l]) atomicAdd(&st->cnt.visited[l], cvis[l]);
+      if (cbp[l]) atomicAdd(&st->cnt.bound_pruned[l], cbp[l]);
     }
   }
   for (int vb = blockIdx.x + gridDim.x; vb < kPersistBlocks; vb += gridDim.x)

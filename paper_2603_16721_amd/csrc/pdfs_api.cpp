@@ -180,9 +180,9 @@ int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, int slot) {
     CK(c, launch_pairs(P, w, s));
     if (tk) CK(c, hipEventRecord(ev[1], s));
     if (h >= 5) {
-      // depths 3..h walked per lane (no seed phase: bound pruning is not
-      // applied below depth 2 here, the answers are the same), over the
-      // unfiltered pair list
+      // depths 3..h expanded wave-wide through prefix rings, over the
+      // unfiltered pair list (no seed phase: in bound mode the incumbent
+      // comes from the walk's own leaves)
       Work wd = w;
       wd.work_pairs = wd.pairs;
       CK(c, launch_use_all_pairs(wd, s));
