@@ -41,7 +41,9 @@ namespace {
 
 constexpr int kLv = kMaxH - 3;   // rings of depths 3..kMaxH-1, frames of depths 3..kMaxH-1
 
-template <int W64>
+// kBound: bound mode (an instance of its own, so that the other modes do
+// not carry its registers)
+template <int W64, bool kBound>
 __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   constexpr int W = 2 * W64;
   constexpr int KR = W <= 4 ? 4 : (W <= 16 ? 2 : 1);
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   int* q_queued = s_q[wib][1];
   const int h = P.h;
   const bool all_pre = P.mode == kPruneNone;
-  const bool bound = P.mode == kPruneBound;
+  constexpr bool bound = kBound;
   unsigned long long inc = 0;   // the round's incumbent key as last seen by this lane
   const bool lit = P.tn_literal != 0;
   const unsigned long long* __restrict__ plist = w.work_pairs;
@@ -471,13 +473,19 @@ int resident_deep(K kernel) {
   return per_cu;
 }
 
-template <int W64>
-hipError_t launch_deep_w(const Problem& P, const Work& w, hipStream_t s) {
-  static const int per_cu = resident_deep(&k_dfs_deep<W64>);
+template <int W64, bool kBound>
+hipError_t launch_deep_b(const Problem& P, const Work& w, hipStream_t s) {
+  static const int per_cu = resident_deep(&k_dfs_deep<W64, kBound>);
   int g = per_cu * (P.n_cu > 0 ? P.n_cu : 1);
   if (g > kPersistBlocks) g = kPersistBlocks;
-  k_dfs_deep<W64><<<g, kBlock, 0, s>>>(P, w);
+  k_dfs_deep<W64, kBound><<<g, kBlock, 0, s>>>(P, w);
   return hipGetLastError();
+}
+
+template <int W64>
+hipError_t launch_deep_w(const Problem& P, const Work& w, hipStream_t s) {
+  return P.mode == kPruneBound ? launch_deep_b<W64, true>(P, w, s)
+                               : launch_deep_b<W64, false>(P, w, s);
 }
 
 }  // namespace
