@@ -350,7 +350,8 @@ def main():
             print(f"[bench] h = {hd} round 1 on h3_G5000: {1e3 * dt:.1f} ms, "
                   f"{st1['visited'][hd]:.3e} leaf visits", file=sys.stderr, flush=True)
         svx.close()
-        # the whole cover (to the cohort's 95 % target) with bound pruning
+        # the whole cover (to the cohort's 95 % target) in bound mode (seed
+        # phase, pair filter and bound pruning at every depth)
         svb = pdfs.Solver(Ti, Ni, wi.n_tumor, wi.n_normal, "bound", 0, stream.cuda_stream)
         for hd in (5, 6):
             svb.wsc(hd, wi.alpha_p, wi.alpha_q, max_rounds=1)

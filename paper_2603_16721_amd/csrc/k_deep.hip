@@ -44,7 +44,7 @@ constexpr int kLv = kMaxH - 3;   // rings of depths 3..kMaxH-1, frames of depths
 // kBound: bound mode (an instance of its own, so that the other modes do
 // not carry its registers)
 template <int W64, bool kBound>
-__global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
+__global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
   constexpr int KR = W <= 4 ? 4 : (W <= 16 ? 2 : 1);
   constexpr int kNone = 0x7fffffff;   // "last index" of an idle lane: masks every candidate
@@ -71,8 +71,11 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
   constexpr bool bound = kBound;
   unsigned long long inc = 0;   // the round's incumbent key as last seen by this lane
   const bool lit = P.tn_literal != 0;
-  const unsigned long long* __restrict__ plist = w.work_pairs;
-  const unsigned long long npairs = st->n_work_pairs;
+  // bound mode: phase 1 expands the seed list, phase 2 the filtered work
+  // list; the other modes run phase 2 over every pair
+  const unsigned long long* __restrict__ plist = phase == 1 ? w.seed_pairs : w.work_pairs;
+  const unsigned long long npairs =
+      phase == 1 ? (st->n_seed < kSeedCap ? st->n_seed : kSeedCap) : st->n_work_pairs;
   const unsigned long long nit = st->n_items;
   const uint32_t nitems = (uint32_t)uniform((int)(nit < w.item_cap ? nit : w.item_cap));
   const int nA_all = uniform(st->nA);
@@ -377,12 +380,26 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
             const int c_lo = uniform((int)w.items[it].c_lo);
             const int c_hi = uniform((int)w.items[it].c_hi);
             const uint32_t batch = (uint32_t)uniform((int)w.items[it].batch);
+            const uint32_t first_chunk = (uint32_t)uniform((int)w.items[it].pad) & 1u;
             const unsigned long long pi = (unsigned long long)batch * kPairBatch + lane;
             bool valid = pi < npairs;
             const unsigned long long e = valid ? plist[pi] : 0ull;
             const int a = (int)(e & 0xffff);
             const int b = (int)((e >> 16) & 0xffff);
+            const int ct = (int)((e >> 32) & 0xffff);
             valid = valid && a < b && b < nA_all;   // list entries always satisfy this
+            if (bound) {
+              // the pair's own bound against the incumbent; its depth-3
+              // visits (sorted indices (idx(b), G-h+2]) once per pair
+              inc = load_incumbent(st);
+              const bool drop = valid && dominated(P.p * ct + qN, a, b, inc);
+              if (first_chunk && lane == 0) cbp[2] += (unsigned long long)__popcll(__ballot(drop));
+              unsigned long long v3 = (valid && !drop) ? (unsigned long long)(P.G - h + 2 - w.act[b]) : 0ull;
+#pragma unroll
+              for (int o = 32; o > 0; o >>= 1) v3 += __shfl_xor(v3, o, 64);
+              if (first_chunk && lane == 0) cvis[3] += v3;
+              valid = valid && !drop;
+            }
             const int ra = valid ? a : 0, rb = valid ? b : 0;   // in-range rows for idle lanes
 #pragma unroll
             for (int k = 0; k < W; ++k)
@@ -390,7 +407,6 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
 #pragma unroll
             for (int i = 0; i < kMaxH; ++i) pix[i] = i == 0 ? ra : (i == 1 ? rb : 0);
             last = valid ? b : kNone;
-            if (bound) inc = load_incumbent(st);
             d = wave_first(valid ? (b + 1 > c_lo ? b + 1 : c_lo) : kNone);
             hi = c_hi;
             have = d < hi;
@@ -450,17 +466,17 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w) {
 #pragma unroll
     for (int i = 0; i < kMaxH; ++i) sl.idx[i] = bidx[i];
   }
-  block_best_to(&w.slots[(size_t)2 * kSlotsPerPhase + blockIdx.x], sl);
+  block_best_to(&w.slots[(size_t)phase * kSlotsPerPhase + blockIdx.x], sl);
   // counters: one atomic per wave and depth
   if (lane == 0) {
-    for (int l = 3; l <= h; ++l) {
-      if (cne[l]) atomicAdd(&st->cnt.nonempty[l], cne[l]);
-      if (l >= 4 && cvis[l]) atomicAdd(&st->cnt.visited[l], cvis[l]);
+    for (int l = 2; l <= h; ++l) {
+      if (l >= 3 && cne[l]) atomicAdd(&st->cnt.nonempty[l], cne[l]);
+      if (l >= 3 && cvis[l]) atomicAdd(&st->cnt.visited[l], cvis[l]);
       if (cbp[l]) atomicAdd(&st->cnt.bound_pruned[l], cbp[l]);
     }
   }
   for (int vb = blockIdx.x + gridDim.x; vb < kPersistBlocks; vb += gridDim.x)
-    if (threadIdx.x == 0) w.slots[(size_t)2 * kSlotsPerPhase + vb] = empty_slot();
+    if (threadIdx.x == 0) w.slots[(size_t)phase * kSlotsPerPhase + vb] = empty_slot();
 }
 
 template <typename K>
@@ -474,28 +490,30 @@ int resident_deep(K kernel) {
 }
 
 template <int W64, bool kBound>
-hipError_t launch_deep_b(const Problem& P, const Work& w, hipStream_t s) {
+hipError_t launch_deep_b(const Problem& P, const Work& w, int phase, hipStream_t s) {
   static const int per_cu = resident_deep(&k_dfs_deep<W64, kBound>);
   int g = per_cu * (P.n_cu > 0 ? P.n_cu : 1);
   if (g > kPersistBlocks) g = kPersistBlocks;
-  k_dfs_deep<W64, kBound><<<g, kBlock, 0, s>>>(P, w);
+  k_dfs_deep<W64, kBound><<<g, kBlock, 0, s>>>(P, w, phase);
   return hipGetLastError();
 }
 
 template <int W64>
-hipError_t launch_deep_w(const Problem& P, const Work& w, hipStream_t s) {
-  return P.mode == kPruneBound ? launch_deep_b<W64, true>(P, w, s)
-                               : launch_deep_b<W64, false>(P, w, s);
+hipError_t launch_deep_w(const Problem& P, const Work& w, int phase, hipStream_t s) {
+  return P.mode == kPruneBound ? launch_deep_b<W64, true>(P, w, phase, s)
+                               : launch_deep_b<W64, false>(P, w, phase, s);
 }
 
 }  // namespace
 
-hipError_t launch_dfs_deep(const Problem& P, const Work& w, hipStream_t s) {
-  if (!w.deepq || P.h < 5 || P.h > kMaxH) return hipErrorInvalidValue;
+hipError_t launch_dfs_deep(const Problem& P, const Work& w, int phase, hipStream_t s) {
+  if (!w.deepq || P.h < 5 || P.h > kMaxH || phase < 1 || phase > 2 ||
+      (phase == 1 && P.mode != kPruneBound))
+    return hipErrorInvalidValue;
   switch (w.w64) {
 #define PDFS_CASE(n) \
   case n:            \
-    return launch_deep_w<n>(P, w, s);
+    return launch_deep_w<n>(P, w, phase, s);
     PDFS_CASE(1) PDFS_CASE(2) PDFS_CASE(3) PDFS_CASE(4) PDFS_CASE(5) PDFS_CASE(6)
     PDFS_CASE(7) PDFS_CASE(8) PDFS_CASE(10) PDFS_CASE(12) PDFS_CASE(14) PDFS_CASE(16)
     PDFS_CASE(18) PDFS_CASE(20)

@@ -227,9 +227,7 @@ __global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
   // counters: one row per block
   unsigned long long v[kTallyN] = {0};
   v[kTNe2] = ne2;
-  // bound mode at h <= 4 counts depth 3 over the pairs that survive the
-  // filter; at h >= 5 every pair is expanded
-  v[kTVis3] = (!kH2 && (P.mode != kPruneBound || P.h >= 5)) ? vis3 : 0;
+  v[kTVis3] = (!kH2 && P.mode != kPruneBound) ? vis3 : 0;
   block_tally_to(w.tallies + (size_t)blockIdx.x * kTallyN, v);
   if (kH2) {
     Slot sl = empty_slot();

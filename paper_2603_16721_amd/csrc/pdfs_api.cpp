@@ -180,15 +180,26 @@ int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, int slot) {
     CK(c, launch_pairs(P, w, s));
     if (tk) CK(c, hipEventRecord(ev[1], s));
     if (h >= 5) {
-      // depths 3..h expanded wave-wide through prefix rings, over the
-      // unfiltered pair list (no seed phase: in bound mode the incumbent
-      // comes from the walk's own leaves)
-      Work wd = w;
-      wd.work_pairs = wd.pairs;
-      CK(c, launch_use_all_pairs(wd, s));
-      CK(c, launch_make_items(P, wd, false, s));
-      if (tk) CK(c, hipEventRecord(ev[2], s));
-      CK(c, launch_dfs_deep(P, wd, s));
+      // depths 3..h expanded wave-wide through prefix rings
+      if (c->prune_mode == PDFS_PRUNE_BOUND) {
+        // as for h <= 4: the highest-count pairs first, then the pairs
+        // whose bound can still reach the incumbent they set
+        CK(c, launch_seed_select(P, w, s));
+        CK(c, launch_make_items(P, w, true, s));
+        if (tk) CK(c, hipEventRecord(ev[2], s));
+        CK(c, launch_dfs_deep(P, w, 1, s));
+        CK(c, launch_filter_pairs(P, w, s));
+        CK(c, launch_make_items(P, w, false, s));
+        CK(c, launch_dfs_deep(P, w, 2, s));
+      } else {
+        // every pair (the work list of the other modes is the pair list)
+        Work wd = w;
+        wd.work_pairs = wd.pairs;
+        CK(c, launch_use_all_pairs(wd, s));
+        CK(c, launch_make_items(P, wd, false, s));
+        if (tk) CK(c, hipEventRecord(ev[2], s));
+        CK(c, launch_dfs_deep(P, wd, 2, s));
+      }
       if (tk) CK(c, hipEventRecord(ev[3], s));
     } else if (h >= 3) {
       if (c->prune_mode == PDFS_PRUNE_BOUND) {
@@ -223,7 +234,8 @@ int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, int slot) {
   // slot phases written this round: 0 = h<=2 kernels, 1 = seed DFS or depth-4
   // tiles, 2 = main DFS
   const int phases = h <= 2 ? 1
-                     : (h >= 5 ? 4 : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 6 : 4));
+                     : (h >= 5 ? (c->prune_mode == PDFS_PRUNE_BOUND ? 6 : 4)
+                               : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 6 : 4));
   // counter rows: 0 = pair table (h >= 2), 1 = seed DFS or depth-4 tiles,
   // 2 = main DFS
   // (h >= 5: the deep walk adds its counters directly)

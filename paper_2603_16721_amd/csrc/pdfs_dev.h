@@ -207,7 +207,7 @@ hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s);
 hipError_t launch_use_all_pairs(const Work& w, hipStream_t s);
 hipError_t launch_dfs(const Problem& P, const Work& w, int phase, hipStream_t s);
 // h = 5..9: wave-wide expansion of every depth through per-depth prefix rings
-hipError_t launch_dfs_deep(const Problem& P, const Work& w, hipStream_t s);
+hipError_t launch_dfs_deep(const Problem& P, const Work& w, int phase, hipStream_t s);
 // two-phase depth-4 (h = 4, empty-prefix pruning): the main DFS lists the
 // non-empty depth-3 prefixes with long candidate streams, they are bucketed
 // by c and expanded in tiles of 64
