@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
   constexpr int kWib = kBlock / kWave;
   __shared__ int s_amax[kMaxH + 1];
   __shared__ unsigned long long s_cnt[kWib][3][kMaxH + 1];   // non-empty, visited, bound-pruned
-  __shared__ int s_q[kWib][2][kLv];   // per ring: entries taken, entries queued
+  // per ring: entries taken, entries queued (running counts, modulo 2^32)
+  __shared__ uint32_t s_q[kWib][2][kLv];
   __shared__ int s_f[kWib][2][kLv];   // per suspended frame: next candidate, end
   RoundState* st = w.st;
   if (st->done) return;
@@ -59,13 +60,13 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
   const int wib = threadIdx.x >> 6;
   if (threadIdx.x <= kMaxH) s_amax[threadIdx.x] = st->amax[threadIdx.x];
   if (lane <= kMaxH) s_cnt[wib][0][lane] = s_cnt[wib][1][lane] = s_cnt[wib][2][lane] = 0ull;
-  if (lane < kLv) s_q[wib][0][lane] = s_q[wib][1][lane] = 0;
+  if (lane < kLv) s_q[wib][0][lane] = s_q[wib][1][lane] = 0u;
   __syncthreads();
   unsigned long long* cne = s_cnt[wib][0];
   unsigned long long* cvis = s_cnt[wib][1];
   unsigned long long* cbp = s_cnt[wib][2];
-  int* q_taken = s_q[wib][0];
-  int* q_queued = s_q[wib][1];
+  uint32_t* q_taken = s_q[wib][0];
+  uint32_t* q_queued = s_q[wib][1];
   const int h = P.h;
   const bool all_pre = P.mode == kPruneNone;
   constexpr bool bound = kBound;
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
     return reinterpret_cast<int*>(area + (size_t)(l - 3) * kRingWords + (size_t)W * kDeepQ);
   };
   auto frame = [&](int l) { return area + kLv * kRingWords + (size_t)(l - 3) * kFrameWords; };
-  auto queued = [&](int l) { return uniform(q_queued[l - 3]) - uniform(q_taken[l - 3]); };
+  auto counter = [&](const uint32_t* c, int l) { return (uint32_t)uniform((int)c[l - 3]); };
+  auto queued = [&](int l) { return (int)(counter(q_queued, l) - counter(q_taken, l)); };
 
   int bs = -1, btp = 0, bfp = 0;
   int bidx[kMaxH];
@@ -123,9 +125,9 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
   auto take = [&](int l, int n) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // written by other lanes
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const int qh = uniform(q_taken[l - 3]);
+    const uint32_t qh = counter(q_taken, l);
     const bool v = lane < n;
-    const int e = (qh + lane) & (kDeepQ - 1);
+    const int e = (int)((qh + (uint32_t)lane) & (kDeepQ - 1));
     const uint32_t* __restrict__ ry = ring_y(l);
     const int* __restrict__ ri = ring_ix(l);
 #pragma unroll
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
       pix[i] = (v && i < l) ? ri[i * kDeepQ + e] : 0;
       if (v && i == l - 1) last = pix[i];
     }
-    q_taken[l - 3] = qh + n;
+    q_taken[l - 3] = qh + (uint32_t)n;
     if (bound) inc = load_incumbent(st);
     L = l + 1;
     d = wave_first(last == kNone ? kNone : last + 1);
@@ -204,19 +206,19 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
                        (unsigned long long)(P.G - h + l - w.act[dd]);
       }
       if (mx) {
-        const int qt = uniform(q_queued[l - 3]);
+        const uint32_t qt = counter(q_queued, l);
         if ((mx >> lane) & 1ull) {
           const int rank = (int)__builtin_amdgcn_mbcnt_hi(
               (uint32_t)(mx >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mx, 0u));
-          const int pos = (qt + rank) & (kDeepQ - 1);
+          const int pos = (int)((qt + (uint32_t)rank) & (kDeepQ - 1));
 #pragma unroll
           for (int k = 0; k < W; ++k) ry[(size_t)k * kDeepQ + pos] = yc[k];
           for (int i = 0; i < l - 1; ++i) ri[i * kDeepQ + pos] = pix[i];
           ri[(l - 1) * kDeepQ + pos] = dd;
         }
-        const int qt2 = qt + __popcll(mx);
+        const uint32_t qt2 = qt + (uint32_t)__popcll(mx);
         q_queued[l - 3] = qt2;
-        full = qt2 - uniform(q_taken[l - 3]) >= kWave;
+        full = (int)(qt2 - counter(q_taken, l)) >= kWave;
       }
     };
     auto group = [&](const uint32_t (&r)[KR][W]) {
