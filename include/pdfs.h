@@ -194,7 +194,11 @@ int32_t pdfs_best_combo(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alp
  * the number of rounds.  If more than cap rounds were needed the call returns
  * PDFS_ERR_TRUNCATED with *n_out = rounds needed (the first cap are written).
  * final_uncovered (host, may be NULL) receives the mask after the last round.
- * stats may be NULL. */
+ * stats may be NULL.  The first call with h >= 5 on a context allocates the
+ * deep walk's prefix rings (about 0.8 GB at 1000 tumour samples), kept until
+ * pdfs_destroy; PDFS_ERR_OUT_OF_MEMORY if that fails.  PDFS_ERR_DEVICE also
+ * reports a device-side consistency failure (a corrupt result slot, or the
+ * deep walk's scheduler making no progress), with the run stopped. */
 int32_t pdfs_wsc_run(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alpha_q,
                      int32_t target_covered, int32_t max_rounds,
                      const uint64_t *initial_uncovered, pdfs_combo *out, int32_t cap,
