@@ -44,3 +44,41 @@ def test_binding_names_match_abi():
     from paper_2603_16721_amd import pdfs
     for n in declared():
         assert n in pdfs.EXPORTS
+
+
+def test_binding_layout_matches_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets, and every PDFS_* constant the binding defines has the header's
+    value (a C program compiled against include/pdfs.h prints them)."""
+    import ctypes as ct
+    from paper_2603_16721_amd import pdfs
+    structs = {n: getattr(pdfs, n) for n in dir(pdfs)
+               if isinstance(getattr(pdfs, n), type) and issubclass(getattr(pdfs, n), ct.Structure)
+               and n.startswith("pdfs_")}
+    assert set(structs) >= {"pdfs_matrix", "pdfs_options", "pdfs_combo", "pdfs_stats"}
+    consts = {n: getattr(pdfs, n) for n in dir(pdfs)
+              if n.startswith("PDFS_") and isinstance(getattr(pdfs, n), int)}
+    consts["PDFS_MAX_H"] = pdfs.MAX_H
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pdfs.h"', "int main(void) {"]
+    for n, cls in sorted(structs.items()):
+        lines.append(f'  printf("{n} size %zu\\n", sizeof({n}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{n}.{f[0]} off %zu\\n", offsetof({n}, {f[0]}));')
+    for n in sorted(consts):
+        lines.append(f'  printf("{n} val %lld\\n", (long long)({n}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        key, kind, v = line.rsplit(" ", 2)
+        got[(key, kind)] = int(v)
+    for n, cls in structs.items():
+        assert got[(n, "size")] == ct.sizeof(cls), n
+        for f in cls._fields_:
+            assert got[(f"{n}.{f[0]}", "off")] == getattr(cls, f[0]).offset, (n, f[0])
+    for n, v in consts.items():
+        assert got[(n, "val")] == v, n
