@@ -109,23 +109,23 @@ def test_wsc_deep(pdfs, case, mode):
 
 
 # The literal reading of T- (TN = normals carrying none of the genes): every
-# leaf path (h = 1 .. 6) in the modes that reach it, against the oracle.
+# leaf path (h = 1 .. 6, and 9) in every mode, against the oracle.
 LITERAL = [c for c in TINY if c[0] in (102, 103, 104, 105, 106, 107, 109, 112, 113, 114, 115)] + \
-    [c for c in DEEP if c[0] in (201, 202)] + [(117, 90, 120, 300, 0.12, 2, (1, 10))]
+    [c for c in DEEP if c[0] in (201, 202, 207)] + [(117, 90, 120, 300, 0.12, 2, (1, 10))]
 
 
 @pytest.mark.parametrize("case", LITERAL, ids=[f"s{c[0]}_h{c[5]}" for c in LITERAL])
-@pytest.mark.parametrize("mode", ["empty", "bound"])
+@pytest.mark.parametrize("mode", ["empty", "bound", "none"])
 def test_wsc_tn_literal(pdfs, case, mode):
     seed, G, nt, nn, d, h, (p, q) = case
     I = synth.random_tiny(seed, G, nt, nn, d, h, alpha=(p, q))
     T, N = I.packed()
-    exp = cpu.wsc(T, N, nt, nn, h, p, q, mode="empty", tn="literal")
+    exp = cpu.wsc(T, N, nt, nn, h, p, q, mode="none" if mode == "none" else "empty", tn="literal")
     with pdfs.Solver(T, N, nt, nn, mode, tn_literal=True) as s:
         got, stats, final = s.wsc(h, p, q)
     _same_rounds(got, exp.rounds)
     assert np.array_equal(final, exp.final_uncovered)
-    if mode == "empty":
+    if mode != "bound":
         _counters_equal(stats, exp.counters, h)
 
 
