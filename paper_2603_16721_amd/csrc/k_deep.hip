@@ -395,7 +395,8 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
               // visits (sorted indices (idx(b), G-h+2]) once per pair
               inc = load_incumbent(st);
               const bool drop = valid && dominated(P.p * ct + qN, a, b, inc);
-              if (first_chunk && lane == 0) cbp[2] += (unsigned long long)__popcll(__ballot(drop));
+              const unsigned long long md = __ballot(drop);
+              if (first_chunk && lane == 0) cbp[2] += (unsigned long long)__popcll(md);
               unsigned long long v3 = (valid && !drop) ? (unsigned long long)(P.G - h + 2 - w.act[b]) : 0ull;
 #pragma unroll
               for (int o = 32; o > 0; o >>= 1) v3 += __shfl_xor(v3, o, 64);
