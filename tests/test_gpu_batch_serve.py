@@ -154,3 +154,66 @@ def test_server_admission_by_memory(pdfs):
             pdfs.pdfs_server_poll(srv, 12345)
         finally:
             pdfs.pdfs_server_destroy(srv)
+
+
+# Deeper combinations through the front ends: one batch (and one server)
+# mixing h = 3, 5 and 6 cohorts; every result equals the oracle's.
+DEEP_MIX = [
+    # seed, G, n_tumor, n_normal, density, h
+    (301, 40, 100, 30, 0.25, 5),
+    (302, 30, 150, 50, 0.35, 6),
+    (303, 60, 120, 40, 0.2, 3),
+]
+ROUND_KEYS = ("sorted_idx", "tp", "fp", "score_num")
+
+
+def _deep_mix():
+    from oracle import cpu
+    insts = [synth.random_tiny(s, G, nt, nn, d, h) for s, G, nt, nn, d, h in DEEP_MIX]
+    exp = []
+    for I in insts:
+        T, N = I.packed()
+        exp.append(cpu.wsc(T, N, I.n_tumor, I.n_normal, I.h, 1, 10, mode="empty").rounds)
+    return insts, exp
+
+
+def _same(got, exp):
+    assert len(got) == len(exp)
+    for g, e in zip(got, exp):
+        assert all(g[k] == e[k] for k in ROUND_KEYS), (g, e)
+
+
+@pytest.mark.parametrize("mode", ["bound", "empty"])
+def test_batched_deep_mix_matches_oracle(pdfs, mode):
+    insts, exp = _deep_mix()
+    b = pdfs.pdfs_batch_create([(*I.packed(), I.n_tumor, I.n_normal) for I in insts], mode)
+    try:
+        for _ in range(2):   # the second run replays captured rounds
+            res, _ = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
+                                         n_tumors=[I.n_tumor for I in insts])
+            for r, e in zip(res, exp):
+                _same(r, e)
+    finally:
+        pdfs.pdfs_batch_destroy(b)
+
+
+def test_served_deep_mix_matches_oracle(pdfs):
+    insts, exp = _deep_mix()
+    srv = pdfs.pdfs_server_create("bound", 0, 0, 4)
+    try:
+        tickets = [pdfs.pdfs_server_submit(srv, *I.packed(), I.n_tumor, I.n_normal, I.h, 1, 10)
+                   for I in insts]
+        out = [None] * len(insts)
+        deadline = time.time() + 120
+        while any(o is None for o in out):
+            for k, t in enumerate(tickets):
+                if out[k] is None:
+                    r = pdfs.pdfs_server_poll(srv, t, cap=insts[k].n_tumor + 1)
+                    if r is not None:
+                        out[k] = r[0]
+            assert time.time() < deadline, "served requests did not finish"
+            time.sleep(0.002)
+    finally:
+        pdfs.pdfs_server_destroy(srv)
+    for r, e in zip(out, exp):
+        _same(r, e)
