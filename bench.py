@@ -353,7 +353,7 @@ def main():
         # the whole cover (to the cohort's 95 % target) in bound mode (seed
         # phase, pair filter and bound pruning at every depth)
         svb = pdfs.Solver(Ti, Ni, wi.n_tumor, wi.n_normal, "bound", 0, stream.cuda_stream)
-        for hd in (5, 6):
+        for hd in (5, 6, 7):
             svb.wsc(hd, wi.alpha_p, wi.alpha_q, max_rounds=1)
             torch.cuda.synchronize()
             tx = time.perf_counter()
