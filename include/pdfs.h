@@ -242,6 +242,10 @@ int32_t pdfs_batch_run(pdfs_batch *b, const int32_t *h, uint32_t alpha_p, uint32
                        const int32_t *target, pdfs_combo *const *outs, const int32_t *caps,
                        int32_t *n_outs, pdfs_stats *stats);
 void pdfs_batch_destroy(pdfs_batch *b);
+/* Detail of the last failing call on b (which instance failed and why);
+ * b = NULL gives the detail of a failed pdfs_batch_create on this thread.
+ * The string stays valid until the next call on b. */
+const char *pdfs_batch_last_error(const pdfs_batch *b);
 
 /* ------------------------------------------------------------- served
  * A request loop: solves submitted at any time are admitted when a slot and
@@ -271,6 +275,12 @@ int32_t pdfs_server_poll(pdfs_server *s, uint64_t ticket, pdfs_combo *out, int32
 /* Blocks until every submitted request has finished. */
 int32_t pdfs_server_drain(pdfs_server *s);
 void pdfs_server_destroy(pdfs_server *s);
+/* Detail of the last failing pdfs_server_submit / pdfs_server_poll on s (for
+ * a failed solve: the ticket and the solve's own error); s = NULL gives the
+ * detail of a failed pdfs_server_create on this thread.  The string is a
+ * per-thread copy, valid until the calling thread's next call of this
+ * function. */
+const char *pdfs_server_last_error(const pdfs_server *s);
 
 #ifdef __cplusplus
 }

@@ -1,7 +1,7 @@
 // Ingest and per-round kernels of the P-DFS / greedy-WSC path.
 //
 //  ingest (once per cohort, Sec. III-B): per-gene combined mutation counts,
-//    stable radix sort -> sparsest-first order, gather of the sorted rows.
+//    stable counting sort -> sparsest-first order, gather of the sorted rows.
 //  round begin / active / gather (Alg. 1 DelCols + Alg. 2 depth 1): the
 //    uncovered sample list, the genes whose row meets it (a gene whose
 //    depth-1 intersection is empty roots no combination with TP >= 1), and
@@ -9,8 +9,6 @@
 //    later intersection runs over ceil(|U|/64) words.
 //  finish (Alg. 1 steps 4-7): exact (S desc, tuple asc) argmax over the
 //    per-wave bests, the round record, and U <- U & ~cover(gamma*).
-#include <hipcub/hipcub.hpp>
-
 #include "pdfs_dev.h"
 #include "slot_reduce.h"
 
@@ -28,7 +26,7 @@ __device__ __forceinline__ bool lex_less(const int32_t* x, const int32_t* y, int
 // ------------------------------------------------------------- ingest
 __global__ void k_gene_counts(const uint64_t* __restrict__ T, int64_t ts,
                               const uint64_t* __restrict__ N, int64_t ns, int G, int wt, int wn,
-                              uint32_t* __restrict__ counts, int32_t* __restrict__ ids) {
+                              uint32_t* __restrict__ counts) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   uint32_t c = 0;
@@ -36,7 +34,85 @@ __global__ void k_gene_counts(const uint64_t* __restrict__ T, int64_t ts,
   if (N)
     for (int w = 0; w < wn; ++w) c += __popcll(N[(size_t)g * ns + w]);
   counts[g] = c;
-  ids[g] = g;
+}
+
+// Sparsest-first order: a stable counting sort of the genes by their combined
+// count (keys 0 .. n_tumor + n_normal), ties by caller index.  Gene g goes to
+//   #{g' : key(g') < key(g)} + #{g' < g : key(g') = key(g)}.
+// Genes are cut into tiles of kSortTile; a tile gives each of its genes the
+// rank among the earlier genes of the tile with the same key, and its per-key
+// counts; one exclusive scan over (key, tile) in key-major order then gives
+// the first position of every (key, tile) group.
+constexpr int kSortTile = 256;
+
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// One block per tile.  tile_hist [ntiles][nkeys] must be zero.
+__global__ __launch_bounds__(kSortTile) void k_sort_tile_ranks(const uint32_t* __restrict__ counts,
+                                                               int G, int nkeys,
+                                                               uint32_t* __restrict__ tile_hist,
+                                                               uint32_t* __restrict__ rank) {
+  __shared__ uint32_t key[kSortTile];
+  const int i = threadIdx.x;
+  const int g = blockIdx.x * kSortTile + i;
+  const uint32_t k = g < G ? counts[g] : 0xffffffffu;
+  key[i] = k;
+  __syncthreads();
+  if (g >= G) return;
+  uint32_t r = 0;
+  bool last = true;
+  for (int j = 0; j < kSortTile; ++j) {
+    const bool same = key[j] == k;
+    r += (same && j < i) ? 1u : 0u;
+    last = last && !(same && j > i);
+  }
+  rank[g] = r;
+  if (last) tile_hist[(size_t)blockIdx.x * nkeys + k] = r + 1;
+}
+
+// One block: tile_hist[t][k] <- first position of the genes of tile t with
+// key k (exclusive scan in the order k major, t minor).
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ tile_hist, int nkeys,
+                                                    int ntiles) {
+  __shared__ uint32_t part[1024];
+  const int tid = threadIdx.x;
+  const size_t n = (size_t)nkeys * ntiles;
+  const size_t per = (n + 1023) / 1024;
+  const size_t lo = (size_t)tid * per < n ? (size_t)tid * per : n;
+  const size_t hi = lo + per < n ? lo + per : n;
+  auto at = [&](size_t e) -> uint32_t& {
+    return tile_hist[(e % (size_t)ntiles) * nkeys + e / (size_t)ntiles];
+  };
+  uint32_t sum = 0;
+  for (size_t e = lo; e < hi; ++e) sum += at(e);
+  part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t add = tid >= o ? part[tid - o] : 0u;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  uint32_t run = part[tid] - sum;
+  for (size_t e = lo; e < hi; ++e) {
+    const uint32_t x = at(e);
+    at(e) = run;
+    run += x;
+  }
+}
+
+__global__ void k_sort_scatter(const uint32_t* __restrict__ counts,
+                               const uint32_t* __restrict__ rank,
+                               const uint32_t* __restrict__ tile_first, int G, int nkeys,
+                               int32_t* __restrict__ perm) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const uint32_t pos = tile_first[(size_t)(g / kSortTile) * nkeys + counts[g]] + rank[g];
+  perm[pos] = g;
 }
 
 __global__ void k_gather_sorted(const uint64_t* __restrict__ T, int64_t ts,
@@ -448,6 +524,11 @@ __global__ void k_run_begin(Problem P, Work w, int max_rounds) {
     st->n_unc = c;
     st->tx_vis3 = st->tx_vis4 = st->tx_leaves = st->tx_fp_leaves = st->tx_pair_macs = 0;
     st->tx_vis_words3 = st->tx_vis_words4 = 0;
+    // nothing of an earlier run (a failed one included) carries over
+    st->overflow = 0;
+    st->found = 0;
+    st->n_tri = 0;
+    st->tri_cursor = 0;
   }
   for (int l = lane; l <= kMaxH; l += 64) {
     st->tot.visited[l] = 0;
@@ -461,16 +542,28 @@ __global__ void k_run_begin(Problem P, Work w, int max_rounds) {
 // ---------------------------------------------------------------- launchers
 hipError_t launch_gene_counts(const uint64_t* T, int64_t ts, const uint64_t* N, int64_t ns,
                               int G, int wt, int wn, uint32_t* counts, hipStream_t s) {
-  // ids share the counts allocation's companion buffer: counts[G..2G) as int
-  int32_t* ids = reinterpret_cast<int32_t*>(counts + G);
-  k_gene_counts<<<(G + 255) / 256, 256, 0, s>>>(T, ts, N, ns, G, wt, wn, counts, ids);
+  k_gene_counts<<<(G + 255) / 256, 256, 0, s>>>(T, ts, N, ns, G, wt, wn, counts);
   return hipGetLastError();
 }
 
-hipError_t sort_genes(uint32_t* counts, uint32_t* counts_tmp, int32_t* ids, int32_t* perm, int G,
-                      void* tmp, size_t* tmp_bytes, hipStream_t s) {
-  return hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, counts, counts_tmp, ids, perm, G, 0,
-                                            32, s);
+size_t sort_tmp_words(int G, int max_key) {
+  const size_t ntiles = (size_t)(G + kSortTile - 1) / kSortTile;
+  return (size_t)G + ntiles * (size_t)(max_key + 1);
+}
+
+hipError_t sort_genes(const uint32_t* counts, int G, int max_key, uint32_t* tmp, int32_t* perm,
+                      hipStream_t s) {
+  const int ntiles = (G + kSortTile - 1) / kSortTile;
+  const int nkeys = max_key + 1;
+  uint32_t* rank = tmp;
+  uint32_t* tile_hist = tmp + G;
+  const size_t nh = (size_t)ntiles * nkeys;
+  k_fill_u32<<<(int)((nh + 255) / 256 < 1024 ? (nh + 255) / 256 : 1024), 256, 0, s>>>(tile_hist,
+                                                                                     nh, 0u);
+  k_sort_tile_ranks<<<ntiles, kSortTile, 0, s>>>(counts, G, nkeys, tile_hist, rank);
+  k_sort_scan<<<1, 1024, 0, s>>>(tile_hist, nkeys, ntiles);
+  k_sort_scatter<<<(G + 255) / 256, 256, 0, s>>>(counts, rank, tile_hist, G, nkeys, perm);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather_sorted(const uint64_t* T, int64_t ts, const uint64_t* N, int64_t ns,

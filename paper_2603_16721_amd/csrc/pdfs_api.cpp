@@ -728,21 +728,16 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
     return bail(PDFS_ERR_INVALID_ARG);
   }
 
-  // Sparsest-first order: stable radix sort of the combined counts.
-  uint32_t* counts = nullptr;   // [G] counts, then [G] ids
-  uint32_t* counts_sorted = nullptr;
-  CKC(dalloc(c, &counts, 2 * (size_t)G));
-  CKC(dalloc(c, &counts_sorted, (size_t)G));
+  // Sparsest-first order: stable counting sort of the combined counts.
+  uint32_t* counts = nullptr;
+  uint32_t* sort_tmp = nullptr;
+  const int max_key = m->n_tumor + m->n_normal;
+  CKC(dalloc(c, &counts, (size_t)G));
+  CKC(dalloc(c, &sort_tmp, sort_tmp_words(G, max_key)));
   CKC(dalloc(c, &c->perm, (size_t)G));
   CKC(launch_gene_counts(dT, m->tumor_stride_words, dN, m->normal_stride_words, G, wt, wn_in,
                          counts, s));
-  size_t tmp_bytes = 0;
-  CKC(sort_genes(counts, counts_sorted, reinterpret_cast<int32_t*>(counts + G), c->perm, G,
-                 nullptr, &tmp_bytes, s));
-  void* tmp = nullptr;
-  CKC(dmalloc(c, &tmp, tmp_bytes));
-  CKC(sort_genes(counts, counts_sorted, reinterpret_cast<int32_t*>(counts + G), c->perm, G, tmp,
-                 &tmp_bytes, s));
+  CKC(sort_genes(counts, G, max_key, sort_tmp, c->perm, s));
   CKC(dalloc(c, &c->Ts, (size_t)G * wt));
   CKC(dalloc(c, &c->Ns, (size_t)G * c->wn));
   CKC(launch_gather_sorted(dT, m->tumor_stride_words, dN, m->normal_stride_words, c->perm, G, wt,
@@ -751,13 +746,9 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   CKC(launch_normal_counts(c->Ns, G, c->wn, c->ncount, s));
   c->h_perm.resize(G);
   CKC(hipMemcpyAsync(c->h_perm.data(), c->perm, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
-  std::vector<uint32_t> h_counts(G);
-  CKC(hipMemcpyAsync(h_counts.data(), counts_sorted, sizeof(uint32_t) * G,
-                     hipMemcpyDeviceToHost, s));
   CKC(hipStreamSynchronize(s));
-  dfree(c, tmp);
+  dfree(c, sort_tmp);
   dfree(c, counts);
-  dfree(c, counts_sorted);
   free_stage();
 
   // Upper bound of the active list: genes with any tumour mutation.

@@ -125,24 +125,45 @@ struct pdfs_batch {
   std::string err;
 };
 
+namespace {
+
+int32_t batch_fail(pdfs_batch* b, int32_t code, const std::string& msg) {
+  b->err = msg;
+  return code;
+}
+
+// The failing instance's own detail.
+int32_t batch_fail(pdfs_batch* b, int32_t code, int inst) {
+  b->err = "instance " + std::to_string(inst) + ": " +
+           (inst >= 0 && inst < (int)b->ctx.size() ? b->ctx[inst]->err : std::string());
+  return code;
+}
+
+}  // namespace
+
 extern "C" {
+
+const char* pdfs_batch_last_error(const pdfs_batch* b) {
+  return b ? b->err.c_str() : create_error().c_str();
+}
 
 int32_t pdfs_batch_create(const pdfs_matrix* inst, int32_t n, const pdfs_options* opt,
                           pdfs_batch** out) {
-  if (!out || !inst || n < 1) return PDFS_ERR_INVALID_ARG;
+  if (!out || !inst || n < 1)
+    return ctx_fail(nullptr, PDFS_ERR_INVALID_ARG, "need out, inst and n >= 1");
   *out = nullptr;
   pdfs_batch* b = new pdfs_batch();
   b->device = opt ? opt->device : 0;
   b->autotune = opt && (opt->flags & PDFS_OPT_AUTOTUNE);
   if (hipSetDevice(b->device) != hipSuccess) {
     delete b;
-    return PDFS_ERR_DEVICE;
+    return ctx_fail(nullptr, PDFS_ERR_DEVICE, "hipSetDevice failed");
   }
   for (int k = 0; k < kStreams; ++k) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       pdfs_batch_destroy(b);
-      return PDFS_ERR_DEVICE;
+      return ctx_fail(nullptr, PDFS_ERR_DEVICE, "hipStreamCreateWithFlags failed");
     }
     b->streams.push_back(s);
   }
@@ -154,8 +175,9 @@ int32_t pdfs_batch_create(const pdfs_matrix* inst, int32_t n, const pdfs_options
     pdfs_ctx* c = nullptr;
     const int32_t rc = create_ctx(&inst[i], &o, &c, nullptr, true);
     if (rc != PDFS_OK) {
+      const std::string why = "instance " + std::to_string(i) + ": " + create_error();
       pdfs_batch_destroy(b);
-      return rc;
+      return ctx_fail(nullptr, rc, why);
     }
     b->ctx.push_back(c);
   }
@@ -166,13 +188,15 @@ int32_t pdfs_batch_create(const pdfs_matrix* inst, int32_t n, const pdfs_options
 int32_t pdfs_batch_run(pdfs_batch* b, const int32_t* h, uint32_t p, uint32_t q,
                        const int32_t* target, pdfs_combo* const* outs, const int32_t* caps,
                        int32_t* n_outs, pdfs_stats* stats) {
-  if (!b || !h || !n_outs) return PDFS_ERR_INVALID_ARG;
+  if (!b) return PDFS_ERR_INVALID_ARG;
+  b->err.clear();
+  if (!h || !n_outs) return batch_fail(b, PDFS_ERR_INVALID_ARG, "h and n_outs must not be NULL");
   const int n = (int)b->ctx.size();
   const auto t0 = Clock::now();
   if (stats) memset(stats, 0, sizeof(*stats));
   for (int i = 0; i < n; ++i) {
     const int32_t rc = check_call(b->ctx[i], h[i], p, q);
-    if (rc != PDFS_OK) return rc;
+    if (rc != PDFS_OK) return batch_fail(b, rc, i);
     n_outs[i] = 0;
   }
   if (b->autotune)
@@ -181,13 +205,14 @@ int32_t pdfs_batch_run(pdfs_batch* b, const int32_t* h, uint32_t p, uint32_t q,
     pdfs_ctx* c = b->ctx[i];
     begin_stats(c, nullptr);
     const int32_t n_unc = set_uncovered(c, nullptr);
-    if (n_unc < 0) return n_unc;
+    if (n_unc < 0) return batch_fail(b, n_unc, i);
     const int K = (target && target[i] > 0) ? target[i] : c->n_tumor;
     const int32_t rc = run_start(c, h[i], p, q, K, 0, n_unc);
-    if (rc != PDFS_OK) return rc;
+    if (rc != PDFS_OK) return batch_fail(b, rc, i);
   }
   // feed every run without blocking until all have stopped
   int32_t first_err = PDFS_OK;
+  int err_inst = -1;
   int remaining = n;
   std::vector<bool> live(n, true);
   while (remaining > 0) {
@@ -195,7 +220,7 @@ int32_t pdfs_batch_run(pdfs_batch* b, const int32_t* h, uint32_t p, uint32_t q,
       if (!live[i]) continue;
       const int32_t rc = run_enqueue(b->ctx[i]);
       if (rc != PDFS_OK) {
-        if (first_err == PDFS_OK) first_err = rc;
+        if (first_err == PDFS_OK) { first_err = rc; err_inst = i; }
         live[i] = false;
         --remaining;
       }
@@ -207,23 +232,26 @@ int32_t pdfs_batch_run(pdfs_batch* b, const int32_t* h, uint32_t p, uint32_t q,
       const int32_t rc = run_poll(b->ctx[i], false, &ready, &done);
       progressed |= ready;
       if (rc != PDFS_OK || done) {
-        if (rc != PDFS_OK && first_err == PDFS_OK) first_err = rc;
+        if (rc != PDFS_OK && first_err == PDFS_OK) { first_err = rc; err_inst = i; }
         live[i] = false;
         --remaining;
       }
     }
     if (!progressed && remaining > 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
-  if (first_err != PDFS_OK) return first_err;
+  if (first_err != PDFS_OK) return batch_fail(b, first_err, err_inst);
   int32_t result = PDFS_OK;
   for (int i = 0; i < n; ++i) {
     pdfs_ctx* c = b->ctx[i];
     int32_t rounds = 0;
     const int cap = caps ? caps[i] : 0;
     const int32_t rc = run_records(c, outs ? outs[i] : nullptr, cap, &rounds);
-    if (rc != PDFS_OK) return rc;
+    if (rc != PDFS_OK) return batch_fail(b, rc, i);
     n_outs[i] = rounds;
-    if (rounds > cap) result = PDFS_ERR_TRUNCATED;
+    if (rounds > cap) {
+      result = PDFS_ERR_TRUNCATED;
+      b->err = "instance " + std::to_string(i) + ": more rounds than its cap";
+    }
     if (stats) {
       pdfs_stats s;
       memset(&s, 0, sizeof(s));
@@ -261,6 +289,7 @@ struct Request {
   pdfs_ctx* ctx = nullptr;
   RoundState* pinned = nullptr;
   int32_t status = PDFS_PENDING;
+  std::string err;               // detail of a failed solve
   std::vector<pdfs_combo> result;
   int32_t rounds = 0;
 };
@@ -283,9 +312,17 @@ struct pdfs_server {
   bool stop = false;
   uint64_t next_ticket = 1;
   int next_stream = 0;
+  hipStream_t admit_stream = nullptr;   // ingest of admitted requests
+  std::string err;   // detail of the last failing call (guarded by mu)
 };
 
 namespace {
+
+int32_t server_fail(pdfs_server* s, int32_t code, const std::string& msg) {
+  std::lock_guard<std::mutex> g(s->mu);
+  s->err = msg;
+  return code;
+}
 
 // Finishes a run: records copied to the request, device memory released.
 void complete(pdfs_server* s, const std::shared_ptr<Request>& r, int32_t status) {
@@ -296,6 +333,8 @@ void complete(pdfs_server* s, const std::shared_ptr<Request>& r, int32_t status)
     r->rounds = rounds;
     r->result.resize((size_t)std::min<int32_t>(rounds, (int32_t)r->result.size()));
   }
+  if (status != PDFS_OK && status != PDFS_ERR_TRUNCATED)
+    r->err = r->ctx ? r->ctx->err : create_error();
   if (r->ctx) {
     pdfs_destroy(r->ctx);
     r->ctx = nullptr;
@@ -331,13 +370,19 @@ bool admit_one(pdfs_server* s) {
     r->pinned = s->pinned_pool.back();
     s->pinned_pool.pop_back();
   }
+  // Ingest (copy, pad check, sort, first active count) runs on the server's
+  // own admission stream, so its synchronisations never wait for the rounds
+  // that running requests have queued; the run then joins a shared stream.
   pdfs_options o{};
   o.prune_mode = s->prune_mode;
   o.device = s->device;
-  o.stream = s->streams[s->next_stream++ % (int)s->streams.size()];
+  o.stream = s->admit_stream;
   o.flags = PDFS_OPT_GRAPHS;
   int32_t rc = create_ctx(&r->m, &o, &r->ctx, r->pinned, true);
-  if (rc == PDFS_OK) rc = check_call(r->ctx, r->h, r->p, r->q);
+  if (rc == PDFS_OK) {
+    r->ctx->stream = s->streams[s->next_stream++ % (int)s->streams.size()];
+    rc = check_call(r->ctx, r->h, r->p, r->q);
+  }
   int32_t n_unc = 0;
   if (rc == PDFS_OK) {
     n_unc = set_uncovered(r->ctx, nullptr);
@@ -395,38 +440,54 @@ void worker_loop(pdfs_server* s) {
 
 extern "C" {
 
+const char* pdfs_server_last_error(const pdfs_server* s) {
+  thread_local std::string copy;
+  if (!s) return create_error().c_str();
+  pdfs_server* m = const_cast<pdfs_server*>(s);
+  std::lock_guard<std::mutex> g(m->mu);
+  copy = s->err;
+  return copy.c_str();
+}
+
 int32_t pdfs_server_create(const pdfs_options* opt, uint64_t hbm_budget_bytes, int32_t max_active,
                            pdfs_server** out) {
-  if (!out) return PDFS_ERR_INVALID_ARG;
+  if (!out) return ctx_fail(nullptr, PDFS_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
+  const int mode = opt ? opt->prune_mode : PDFS_PRUNE_BOUND;
+  if (mode < PDFS_PRUNE_NONE || mode > PDFS_PRUNE_BOUND)
+    return ctx_fail(nullptr, PDFS_ERR_INVALID_ARG, "unknown prune mode");
   pdfs_server* s = new pdfs_server();
   s->device = opt ? opt->device : 0;
-  s->prune_mode = opt ? opt->prune_mode : PDFS_PRUNE_BOUND;
+  s->prune_mode = mode;
   s->max_active = max_active > 0 ? max_active : 8;
   if (hipSetDevice(s->device) != hipSuccess) {
     delete s;
-    return PDFS_ERR_DEVICE;
+    return ctx_fail(nullptr, PDFS_ERR_DEVICE, "hipSetDevice failed");
   }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
     delete s;
-    return PDFS_ERR_DEVICE;
+    return ctx_fail(nullptr, PDFS_ERR_DEVICE, "hipMemGetInfo failed");
   }
   s->budget = hbm_budget_bytes ? (size_t)hbm_budget_bytes : free_b / 10 * 9;
   for (int k = 0; k < kStreams; ++k) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
       pdfs_server_destroy(s);
-      return PDFS_ERR_DEVICE;
+      return ctx_fail(nullptr, PDFS_ERR_DEVICE, "hipStreamCreateWithFlags failed");
     }
     s->streams.push_back(st);
+  }
+  if (hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking) != hipSuccess) {
+    pdfs_server_destroy(s);
+    return ctx_fail(nullptr, PDFS_ERR_DEVICE, "hipStreamCreateWithFlags failed");
   }
   for (int k = 0; k < s->max_active; ++k) {
     RoundState* p = nullptr;
     if (hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(RoundState), hipHostMallocDefault) !=
         hipSuccess) {
       pdfs_server_destroy(s);
-      return PDFS_ERR_OUT_OF_MEMORY;
+      return ctx_fail(nullptr, PDFS_ERR_OUT_OF_MEMORY, "pinned round-state pool");
     }
     s->pinned_pool.push_back(p);
   }
@@ -437,13 +498,17 @@ int32_t pdfs_server_create(const pdfs_options* opt, uint64_t hbm_budget_bytes, i
 
 int32_t pdfs_server_submit(pdfs_server* s, const pdfs_matrix* m, int32_t h, uint32_t p,
                            uint32_t q, int32_t target, uint64_t* ticket) {
-  if (!s || !m || !ticket || m->on_device) return PDFS_ERR_INVALID_ARG;
-  if (m->G < 1 || m->n_tumor < 1 || m->n_normal < 0 || !m->tumor) return PDFS_ERR_INVALID_ARG;
+  if (!s) return PDFS_ERR_INVALID_ARG;
+  if (!m || !ticket || m->on_device)
+    return server_fail(s, PDFS_ERR_INVALID_ARG, "need a host matrix and a ticket pointer");
+  if (m->G < 1 || m->n_tumor < 1 || m->n_normal < 0 || !m->tumor)
+    return server_fail(s, PDFS_ERR_INVALID_ARG, "need G >= 1, n_tumor >= 1, n_normal >= 0");
   const int wt = (m->n_tumor + 63) / 64;
   const int wn = m->n_normal > 0 ? (m->n_normal + 63) / 64 : 0;
   if (m->tumor_stride_words < wt || (wn && (!m->normal || m->normal_stride_words < wn)))
-    return PDFS_ERR_INVALID_ARG;
-  if (h < 1 || h > PDFS_MAX_H || h > m->G || q < 1) return PDFS_ERR_INVALID_ARG;
+    return server_fail(s, PDFS_ERR_INVALID_ARG, "matrix stride below the row length");
+  if (h < 1 || h > PDFS_MAX_H || h > m->G || q < 1)
+    return server_fail(s, PDFS_ERR_INVALID_ARG, "h out of range or alpha_q < 1");
   auto r = std::make_shared<Request>();
   r->t_submit = Clock::now();
   r->h = h; r->p = p; r->q = q; r->target = target;
@@ -472,7 +537,11 @@ int32_t pdfs_server_submit(pdfs_server* s, const pdfs_matrix* m, int32_t h, uint
   r->m.normal_stride_words = wn;
   r->bytes = footprint_bytes(m->G, m->n_tumor, m->n_normal, nA, h, s->prune_mode);
   std::lock_guard<std::mutex> g(s->mu);
-  if (r->bytes > s->budget) return PDFS_ERR_OUT_OF_MEMORY;
+  if (r->bytes > s->budget) {
+    s->err = "request footprint " + std::to_string(r->bytes) + " B above the server budget " +
+             std::to_string(s->budget) + " B";
+    return PDFS_ERR_OUT_OF_MEMORY;
+  }
   r->ticket = s->next_ticket++;
   s->queue.push_back(r);
   s->tickets[r->ticket] = r;
@@ -486,10 +555,14 @@ int32_t pdfs_server_poll(pdfs_server* s, uint64_t ticket, pdfs_combo* out, int32
   if (!s) return PDFS_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> g(s->mu);
   auto it = s->tickets.find(ticket);
-  if (it == s->tickets.end()) return PDFS_ERR_INVALID_ARG;
+  if (it == s->tickets.end()) {
+    s->err = "unknown ticket " + std::to_string(ticket);
+    return PDFS_ERR_INVALID_ARG;
+  }
   auto r = it->second;
   if (r->status == PDFS_PENDING) return PDFS_PENDING;
   const int32_t status = r->status;
+  if (status != PDFS_OK) s->err = "ticket " + std::to_string(ticket) + ": " + r->err;
   if (status == PDFS_OK) {
     const int n = std::min<int32_t>(cap, (int32_t)r->result.size());
     for (int i = 0; i < n && out; ++i) out[i] = r->result[(size_t)i];
@@ -498,7 +571,10 @@ int32_t pdfs_server_poll(pdfs_server* s, uint64_t ticket, pdfs_combo* out, int32
   if (latency_ns)
     *latency_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(r->t_done - r->t_submit).count();
   s->tickets.erase(it);
-  if (status == PDFS_OK && r->rounds > cap) return PDFS_ERR_TRUNCATED;
+  if (status == PDFS_OK && r->rounds > cap) {
+    s->err = "ticket " + std::to_string(ticket) + ": more rounds than cap";
+    return PDFS_ERR_TRUNCATED;
+  }
   return status;
 }
 
@@ -519,6 +595,7 @@ void pdfs_server_destroy(pdfs_server* s) {
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->device);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
   for (RoundState* p : s->pinned_pool) (void)hipHostFree(p);
   delete s;
 }

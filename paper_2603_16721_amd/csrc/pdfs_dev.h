@@ -185,8 +185,12 @@ struct Work {
 // create time
 hipError_t launch_gene_counts(const uint64_t* T, int64_t ts, const uint64_t* N, int64_t ns,
                               int G, int wt, int wn, uint32_t* counts, hipStream_t s);
-hipError_t sort_genes(uint32_t* counts, uint32_t* counts_tmp, int32_t* ids, int32_t* perm, int G,
-                      void* tmp, size_t* tmp_bytes, hipStream_t s);
+// Stable counting sort by count (keys 0..max_key), ties by caller index:
+// perm[i] = caller gene at sorted position i.  tmp: sort_tmp_words(G, max_key)
+// words of device scratch.
+size_t sort_tmp_words(int G, int max_key);
+hipError_t sort_genes(const uint32_t* counts, int G, int max_key, uint32_t* tmp, int32_t* perm,
+                      hipStream_t s);
 hipError_t launch_gather_sorted(const uint64_t* T, int64_t ts, const uint64_t* N, int64_t ns,
                                 const int32_t* perm, int G, int wt, int wn, uint64_t* Ts,
                                 uint64_t* Ns, hipStream_t s);

@@ -71,7 +71,8 @@ EXPORTS = ["pdfs_create", "pdfs_destroy", "pdfs_set_prune_mode", "pdfs_best_comb
            "pdfs_wsc_run", "pdfs_strerror", "pdfs_last_error",
            "pdfs_batch_create", "pdfs_batch_run", "pdfs_batch_destroy",
            "pdfs_server_create", "pdfs_server_submit", "pdfs_server_poll", "pdfs_server_drain",
-           "pdfs_server_destroy", "pdfs_measure_int_peak"]
+           "pdfs_server_destroy", "pdfs_measure_int_peak", "pdfs_batch_last_error",
+           "pdfs_server_last_error"]
 PDFS_OPT_GRAPHS = 2
 PDFS_OPT_AUTOTUNE = 4
 PDFS_OPT_TN_LITERAL = 8
@@ -123,6 +124,10 @@ def _load():
     L.pdfs_server_drain.restype = i32
     L.pdfs_server_destroy.argtypes = [P]
     L.pdfs_server_destroy.restype = None
+    L.pdfs_batch_last_error.argtypes = [P]
+    L.pdfs_batch_last_error.restype = ctypes.c_char_p
+    L.pdfs_server_last_error.argtypes = [P]
+    L.pdfs_server_last_error.restype = ctypes.c_char_p
     L.pdfs_measure_int_peak.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
     L.pdfs_measure_int_peak.restype = i32
     return L
@@ -305,7 +310,7 @@ def pdfs_batch_create(instances, prune_mode="bound", device=0, autotune=False):
     rc = lib.pdfs_batch_create(arr, len(mats), ctypes.byref(opt), ctypes.byref(out))
     del keep
     if rc != PDFS_OK:
-        raise PdfsError(rc, lib.pdfs_last_error(None).decode())
+        raise PdfsError(rc, lib.pdfs_batch_last_error(None).decode())
     return out.value
 
 
@@ -325,7 +330,7 @@ def pdfs_batch_run(batch, hs, alpha_p, alpha_q, targets=None, caps=None, n_tumor
     rc = lib.pdfs_batch_run(batch, h_arr, alpha_p, alpha_q, t_arr, outs, c_arr, n_out,
                             ctypes.byref(st))
     if rc != PDFS_OK:
-        raise PdfsError(rc)
+        raise PdfsError(rc, lib.pdfs_batch_last_error(batch).decode())
     res = [[combo_dict(bufs[i][k]) for k in range(n_out[i])] for i in range(n)]
     return res, stats_dict(st, max(hs))
 
@@ -341,7 +346,7 @@ def pdfs_server_create(prune_mode="bound", device=0, hbm_budget_bytes=0, max_act
     rc = lib.pdfs_server_create(ctypes.byref(opt), hbm_budget_bytes, max_active,
                                 ctypes.byref(out))
     if rc != PDFS_OK:
-        raise PdfsError(rc)
+        raise PdfsError(rc, lib.pdfs_server_last_error(None).decode())
     return out.value
 
 
@@ -352,7 +357,7 @@ def pdfs_server_submit(server, tumor, normal, n_tumor, n_normal, h, alpha_p, alp
                                 ctypes.byref(ticket))
     del keep
     if rc != PDFS_OK:
-        raise PdfsError(rc)
+        raise PdfsError(rc, lib.pdfs_server_last_error(server).decode())
     return ticket.value
 
 
@@ -365,7 +370,7 @@ def pdfs_server_poll(server, ticket, cap=4096):
     if rc == PDFS_PENDING:
         return None
     if rc != PDFS_OK:
-        raise PdfsError(rc)
+        raise PdfsError(rc, lib.pdfs_server_last_error(server).decode())
     return [combo_dict(buf[k]) for k in range(n_out.value)], lat.value * 1e-9
 
 

@@ -338,3 +338,68 @@ def test_modes_identical_h3_workload_first_rounds():
     e = cpu.wsc(T, N, I.n_tumor, I.n_normal, 3, 1, 10, max_rounds=2, mode="empty")
     b = cpu.wsc(T, N, I.n_tumor, I.n_normal, 3, 1, 10, max_rounds=2, mode="bound")
     assert e.rounds == b.rounds
+
+
+def _bf_best_first_in(tumor, normal, h, p, q, unc, lo, hi):
+    """Brute-force argmax over the h-subsets whose first sorted index lies in
+    [lo, hi) (the plain definition, restricted the way one rank's share of the
+    outer loop is, Sec. III-D)."""
+    order = bf.sparse_first_order(tumor, normal)
+    Tu = tumor[order][:, unc]
+    Ns = normal[order]
+    best = None
+    for combo in itertools.combinations(range(tumor.shape[0]), h):
+        if not (lo <= combo[0] < hi):
+            continue
+        c = list(combo)
+        tp = int(np.all(Tu[c], axis=0).sum())
+        if tp == 0:
+            continue
+        fp = int(np.all(Ns[c], axis=0).sum()) if normal.shape[1] else 0
+        s = p * tp + q * (normal.shape[1] - fp)
+        if best is None or s > best[3]:
+            best = (combo, tp, fp, s)
+    return best
+
+
+@pytest.mark.parametrize("case", TINY_CASES)
+@pytest.mark.parametrize("mode", ["none", "empty", "bound"])
+def test_best_share_partition(case, mode):
+    """The outer loop cut into g1 shares (Sec. III-D's intervals): every share
+    equals the brute force restricted to first indices in it, the best over
+    the shares under (S desc, tuple asc) is the whole round's, and in the
+    modes whose counters do not depend on an incumbent (exhaustive, empty)
+    the shares' counters add up to the whole round's."""
+    I = _tiny(case)
+    T, N = I.packed()
+    rng = np.random.default_rng(100 + case[0])
+    for trial in range(2):
+        unc = np.ones(I.n_tumor, bool) if trial == 0 else rng.random(I.n_tumor) < 0.6
+        U = mask_of_bits(unc)
+        whole = cpu.best(T, N, I.n_tumor, I.n_normal, I.h, I.alpha_p, I.alpha_q, U=U, mode=mode)
+        cuts = sorted(set([0, I.G] + [int(x) for x in rng.integers(0, I.G + 1, size=3)]))
+        merged = None
+        sums = {"visited": [0] * (cpu.MAX_H + 1), "nonempty": [0] * (cpu.MAX_H + 1)}
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            b = cpu.best_share(T, N, I.n_tumor, I.n_normal, I.h, I.alpha_p, I.alpha_q, lo, hi,
+                               U=U, mode=mode)
+            ref = _bf_best_first_in(I.tumor, I.normal, I.h, I.alpha_p, I.alpha_q, unc, lo, hi)
+            if ref is None:
+                assert not b.found
+            else:
+                assert b.found and b.sorted_idx == ref[0]
+                assert (b.tp, b.fp, b.score) == (ref[1], ref[2], ref[3])
+                if merged is None or (b.score, [-i for i in b.sorted_idx]) > \
+                        (merged.score, [-i for i in merged.sorted_idx]):
+                    merged = b
+            for k in sums:
+                sums[k] = [x + y for x, y in zip(sums[k], b.counters[k])]
+        if merged is None:
+            assert not whole.found
+        else:
+            assert whole.found and merged.sorted_idx == whole.sorted_idx
+            assert (merged.tp, merged.fp, merged.score) == (whole.tp, whole.fp, whole.score)
+        if mode != "bound":
+            for k in sums:
+                # depth 1 is the outer loop itself: its nodes are split, not repeated
+                assert sums[k] == whole.counters[k], (k, sums[k], whole.counters[k])
