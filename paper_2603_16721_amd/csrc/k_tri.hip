@@ -163,8 +163,15 @@ __global__ __launch_bounds__(256) void k_scatter_c(Work w) {
 constexpr int kGrabIters = 2048;   // candidate rows worth one cursor step
 constexpr int kMaxGrab = 16;
 
+// Widest row at which the tile kernel is built for three waves per SIMD
+// (wider: two, with the register room to hold its rows without spilling).
+#ifndef PDFS_TILE3_MAX_W64
+#define PDFS_TILE3_MAX_W64 16
+#endif
+
 template <int W64>
-__global__ __launch_bounds__(256, (W64 <= 16 ? 3 : 2)) void k_dfs4_tiles(Problem P, Work w) {
+__global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_dfs4_tiles(Problem P,
+                                                                                        Work w) {
   constexpr int W = 2 * W64;
   RoundState* st = w.st;
   if (st->done) return;

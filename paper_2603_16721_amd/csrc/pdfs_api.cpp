@@ -59,11 +59,13 @@ void release(pdfs_ctx* c) {
                   c->items, c->slots, c->tallies, c->st, c->recs, c->tri, c->tri_s,
                   c->c_hist, c->deepq};
   for (void* p : ptrs) dfree(c, p);
-  if (c->h_st && c->own_h_st) (void)hipHostFree(c->h_st);
-  for (auto& row : c->ev)
-    for (hipEvent_t e : row)
-      if (e) (void)hipEventDestroy(e);
-  if (c->chunk_done) (void)hipEventDestroy(c->chunk_done);
+  if (c->h_slots && c->own_h_st) (void)hipHostFree(c->h_slots);
+  for (auto& set : c->ev)
+    for (auto& row : set)
+      for (hipEvent_t e : row)
+        if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->chunk_done)
+    if (e) (void)hipEventDestroy(e);
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
 }
@@ -164,11 +166,10 @@ Problem make_problem(const pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
 }
 
 // Enqueues one greedy round (every kernel returns at once if the run is
-// already done).  slot = which event set to use when timing.
-int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, int slot) {
+// already done).  ev = the round's five timing events (used when timing).
+int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, hipEvent_t* ev) {
   const int h = P.h;
   hipStream_t s = c->stream;
-  hipEvent_t* ev = c->ev[slot];
   const bool tk = c->time_kernels;
   CK(c, launch_round_begin(P, w, s));
   CK(c, launch_active(P, w, s));
@@ -254,8 +255,9 @@ namespace pdfs {
 int32_t ctx_fail(pdfs_ctx* c, int32_t code, const std::string& msg) { return fail(c, code, msg); }
 
 // Enqueues `chunk` rounds at the run's current row width: replays of one
-// captured round when graphs are on, direct launches otherwise.
-static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int chunk) {
+// captured round when graphs are on, direct launches otherwise.  slot = the
+// chunk's event set when timing.
+static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int chunk, int slot) {
   const Run& r = c->run;
   if (c->use_graphs && !c->time_kernels) {
     const auto key = std::make_tuple(P.h, w.w64, r.p, r.q, r.target, c->prune_mode,
@@ -265,7 +267,7 @@ static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int 
       hipGraph_t g = nullptr;
       hipGraphExec_t e = nullptr;
       CK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-      const int32_t rc = enqueue_round(c, P, w, 0);
+      const int32_t rc = enqueue_round(c, P, w, c->ev[slot][0]);
       hipGraph_t g2 = nullptr;
       const hipError_t ec = hipStreamEndCapture(c->stream, &g2);
       if (rc != PDFS_OK) {
@@ -282,7 +284,7 @@ static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int 
     return PDFS_OK;
   }
   for (int k = 0; k < chunk; ++k) {
-    const int32_t rc = enqueue_round(c, P, w, k);
+    const int32_t rc = enqueue_round(c, P, w, c->ev[slot][k]);
     if (rc != PDFS_OK) return rc;
   }
   return PDFS_OK;
@@ -313,10 +315,11 @@ static int32_t size_triples(pdfs_ctx* c, int h, int n_unc) {
   CK(c, launch_make_items(P, w, false, s));
   CK(c, launch_tri_begin(w, s));
   CK(c, launch_count_long(P, w, s));
-  CK(c, hipMemcpyAsync(c->h_st, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
+  RoundState* hs = &c->h_slots[c->next_slot];
+  CK(c, hipMemcpyAsync(hs, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
   CK(c, hipStreamSynchronize(s));
-  if (c->h_st->overflow) return PDFS_OK;   // the run itself reports it
-  const unsigned long long need = c->h_st->n_tri;
+  if (hs->overflow) return PDFS_OK;   // the run itself reports it
+  const unsigned long long need = hs->n_tri;
   if (need > c->tri_cap) {
     const unsigned long long cap = need + need / 16 + 1024;
     size_t free_b = 0, total_b = 0;
@@ -344,66 +347,82 @@ int32_t run_start(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int ma
   rc = size_triples(c, h, n_unc);
   if (rc != PDFS_OK) return rc;
   Run& r = c->run;
+  // chunks of an earlier run still in flight are no-ops queued before
+  // this run's work; their slots are simply reused in stream order
   r = Run();
   r.h = h; r.p = p; r.q = q; r.target = target; r.max_rounds = max_rounds; r.n_unc = n_unc;
   const Problem P = make_problem(c, h, p, q);
   Work w0 = make_work(c, 1, target);
   CK(c, launch_run_begin(P, w0, max_rounds, c->stream));
   r.active = true;
+  r.t_prev = std::chrono::steady_clock::now();
   return PDFS_OK;
 }
 
-// The greedy loop on the device.  Rounds are enqueued in growing chunks;
-// between chunks the host reads the run state once (done flag, covered count)
-// and picks the row width of the next chunk: any width >= ceil(|U|/64) gives
-// the same results, and |U| only shrinks, so a chunk may keep its width.
+// The greedy loop on the device.  Chunks of rounds are queued until kDepth
+// are in flight; each takes its row width from the newest |U| the host has
+// read (any width >= ceil(|U|/64) gives the same results, and |U| only
+// shrinks).  Rounds past a round cap are not queued at all.
 int32_t run_enqueue(pdfs_ctx* c) {
   Run& r = c->run;
-  if (!r.active || r.pending) return PDFS_OK;
-  const int w64 = dfs_row_words(words(r.n_unc > 0 ? r.n_unc : 1));
-  if (w64 < 0 || w64 > c->w64_max) return fail(c, PDFS_ERR_UNSUPPORTED, "row too wide");
-  const Problem P = make_problem(c, r.h, r.p, r.q);
-  const Work w = make_work(c, w64, r.target);
-  int32_t rc = enqueue_rounds(c, P, w, r.chunk);
-  if (rc != PDFS_OK) return rc;
-  CK(c, hipMemcpyAsync(c->h_st, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, c->stream));
-  CK(c, hipEventRecord(c->chunk_done, c->stream));
-  r.chunk_w64 = w64;
-  r.pending = true;
+  while (r.active && r.inflight < kDepth) {
+    if (r.max_rounds > 0 && r.enqueued >= r.max_rounds) break;
+    const int w64 = dfs_row_words(words(r.n_unc > 0 ? r.n_unc : 1));
+    if (w64 < 0 || w64 > c->w64_max) return fail(c, PDFS_ERR_UNSUPPORTED, "row too wide");
+    int n = r.chunk;
+    if (r.max_rounds > 0 && n > r.max_rounds - r.enqueued) n = r.max_rounds - r.enqueued;
+    const int slot = c->next_slot;
+    const Problem P = make_problem(c, r.h, r.p, r.q);
+    const Work w = make_work(c, w64, r.target);
+    const int32_t rc = enqueue_rounds(c, P, w, n, slot);
+    if (rc != PDFS_OK) return rc;
+    CK(c, hipMemcpyAsync(&c->h_slots[slot], c->st, sizeof(RoundState), hipMemcpyDeviceToHost,
+                         c->stream));
+    CK(c, hipEventRecord(c->chunk_done[slot], c->stream));
+    c->chunk_rounds[slot] = n;
+    c->next_slot = (slot + 1) % kDepth;
+    r.enqueued += n;
+    r.inflight += 1;
+  }
   return PDFS_OK;
 }
 
+// Reads the oldest chunk in flight (waits for it when wait is true).
 int32_t run_poll(pdfs_ctx* c, bool wait, bool* ready, bool* done) {
   Run& r = c->run;
   *ready = false;
   *done = !r.active;
-  if (!r.active || !r.pending) return PDFS_OK;
+  if (!r.active || r.inflight == 0) return PDFS_OK;
+  const int slot = (c->next_slot - r.inflight + kDepth) % kDepth;
   if (wait) {
-    CK(c, hipEventSynchronize(c->chunk_done));
+    CK(c, hipEventSynchronize(c->chunk_done[slot]));
   } else {
-    const hipError_t q = hipEventQuery(c->chunk_done);
+    const hipError_t q = hipEventQuery(c->chunk_done[slot]);
     if (q == hipErrorNotReady) return PDFS_OK;
     CK(c, q);
   }
   *ready = true;
-  r.pending = false;
+  r.inflight -= 1;
+  c->h_st = &c->h_slots[slot];
   const RoundState& st = *c->h_st;
+  const int chunk = c->chunk_rounds[slot];
+  const int ran = st.executed - r.executed_before;
   if (c->time_kernels) {
-    const int ran = st.executed - r.executed_before;
-    for (int k = 0; k < ran && k < r.chunk; ++k) {
+    for (int k = 0; k < ran && k < chunk; ++k) {
+      hipEvent_t* ev = c->ev[slot][k];
       float ms = 0.f;
       if (r.h >= 2) {
-        CK(c, hipEventElapsedTime(&ms, c->ev[k][0], c->ev[k][1]));
+        CK(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
         c->kernel_ns[0] += (int64_t)(ms * 1e6);
         c->kernel_launches[0] += 1;
       }
       if (r.h >= 3) {
-        CK(c, hipEventElapsedTime(&ms, c->ev[k][2], c->ev[k][3]));
+        CK(c, hipEventElapsedTime(&ms, ev[2], ev[3]));
         c->kernel_ns[1] += (int64_t)(ms * 1e6);
         c->kernel_launches[1] += 1;
       }
       if (r.h >= 3 && c->two_phase) {
-        CK(c, hipEventElapsedTime(&ms, c->ev[k][4], c->ev[k][3]));
+        CK(c, hipEventElapsedTime(&ms, ev[4], ev[3]));
         c->kernel_ns[2] += (int64_t)(ms * 1e6);
         c->kernel_launches[2] += 1;
       }
@@ -426,13 +445,26 @@ int32_t run_poll(pdfs_ctx* c, bool wait, bool* ready, bool* done) {
     r.active = false;
     return fail(c, PDFS_ERR_DEVICE, "greedy loop did not stop");
   }
-  if (st.done) {
+  if (st.done || (r.max_rounds > 0 && r.enqueued >= r.max_rounds && r.inflight == 0)) {
     r.active = false;
     *done = true;
     return PDFS_OK;
   }
   r.n_unc = c->n_tumor - st.covered;
-  r.chunk = r.chunk * 2 < kMaxChunk ? r.chunk * 2 : kMaxChunk;
+  // Chunk length: about kChunkNs of device work per chunk, from the time
+  // between the last two chunk ends (the device had the next chunk queued,
+  // so that interval is this chunk's device time when the host kept up).
+  const auto now = std::chrono::steady_clock::now();
+  const double ns = (double)std::chrono::duration_cast<std::chrono::nanoseconds>(now - r.t_prev).count();
+  r.t_prev = now;
+  constexpr double kChunkNs = 1.0e6;
+  if (ran > 0) {
+    const double per_round = ns / ran;
+    int n = per_round > 0 ? (int)(kChunkNs / per_round) : kMaxChunk;
+    n = n < 1 ? 1 : (n > kMaxChunk ? kMaxChunk : n);
+    // grow at most twofold per chunk so that one fast read does not jump far
+    r.chunk = n > 2 * r.chunk ? 2 * r.chunk : n;
+  }
   return PDFS_OK;
 }
 
@@ -618,7 +650,7 @@ void pdfs_destroy(pdfs_ctx* c) {
   // A context with stream-ordered memory frees in stream order; its own work
   // must be finished (callers destroy it once its run has stopped), but other
   // work sharing the stream need not be waited for.
-  if (c->run.pending || !c->async_alloc) {
+  if (c->run.inflight > 0 || !c->async_alloc) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
   }
@@ -683,9 +715,10 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   hipStream_t s = c->stream;
   const int G = m->G;
   if (c->time_kernels)
-    for (auto& row : c->ev)
-      for (hipEvent_t& e : row) CKC(hipEventCreate(&e));
-  CKC(hipEventCreateWithFlags(&c->chunk_done, hipEventDisableTiming));
+    for (auto& set : c->ev)
+      for (auto& row : set)
+        for (hipEvent_t& e : row) CKC(hipEventCreate(&e));
+  for (hipEvent_t& e : c->chunk_done) CKC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   c->use_graphs = c->stream != nullptr && opt && (opt->flags & PDFS_OPT_GRAPHS);
 
   // Stage the caller's matrices on the device (strided as given).
@@ -763,12 +796,13 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   CKC(dalloc(c, &c->hist, (size_t)kMaxCount + 1));
   CKC(dalloc(c, &c->tallies, (size_t)kSlotPhases * kPersistBlocks * kTallyN));
   if (pinned_state) {
-    c->h_st = pinned_state;
+    c->h_slots = pinned_state;
     c->own_h_st = false;
   } else {
-    CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_st), sizeof(RoundState),
+    CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_slots), kDepth * sizeof(RoundState),
                       hipHostMallocDefault));
   }
+  c->h_st = &c->h_slots[0];
 
   CKC(hipMemsetAsync(c->st, 0, sizeof(RoundState), s));
   CKC(launch_clear_slots(c->slots, kSlotPhases * kSlotsPerPhase, s));

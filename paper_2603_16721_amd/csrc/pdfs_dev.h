@@ -40,7 +40,10 @@ constexpr int kSeedCap = 1024;     // seed list capacity (ties at the threshold)
 constexpr int kMaxCount = 1280;    // largest tumour count of a pair (n_tumor limit)
 // two-phase depth 4: depth-3 prefixes with at least this many depth-4
 // candidates left are listed and expanded in sorted tiles
-constexpr int kLongStream = 384;
+#ifndef PDFS_LONG_STREAM
+#define PDFS_LONG_STREAM 384
+#endif
+constexpr int kLongStream = PDFS_LONG_STREAM;
 
 enum PruneMode { kPruneNone = 0, kPruneEmpty = 1, kPruneBound = 2 };
 

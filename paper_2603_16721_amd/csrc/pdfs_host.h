@@ -16,22 +16,31 @@ namespace pdfs {
 
 int dfs_row_words(int n);
 
-// Rounds enqueued between two reads of the device state (the chunk grows from
-// 2 to this many).  Rounds queued past the stop are no-ops on the device.
+// Rounds of one chunk (enqueued between two reads of the device state) are
+// at most this many; rounds queued past the stop are no-ops on the device.
 constexpr int kMaxChunk = 16;
+// Chunks in flight at once: while the host reads the state after one chunk,
+// the next is already queued, so the device does not wait for the host.
+constexpr int kDepth = 2;
 
-// Progress of one greedy run on a context, advanced without blocking.
+// Progress of one greedy run on a context, advanced without blocking.  The
+// run's rounds go out in chunks; each chunk ends with a copy of the device
+// state into its pinned slot and an event.  The row width of a chunk comes
+// from the newest |U| the host has seen (any width >= ceil(|U|/64) gives the
+// same results and |U| only shrinks), so with kDepth chunks in flight the
+// width lags the device by at most the chunks still queued.
 struct Run {
   bool active = false;      // started and not finished
-  bool pending = false;     // a chunk is in flight
   int h = 0;
   uint32_t p = 1, q = 1;
   int target = 0, max_rounds = 0;
   int n_unc = 0;            // |U| known to the host (only shrinks)
-  int chunk = 2;
-  int chunk_w64 = 0;
+  int chunk = 1;            // rounds in the next chunk
+  int enqueued = 0;         // rounds enqueued by this run
+  int inflight = 0;         // chunks queued and not yet read
   int executed_before = 0;
   int32_t status = PDFS_OK;
+  std::chrono::steady_clock::time_point t_prev;   // when the host last saw a chunk end
 };
 
 }  // namespace pdfs
@@ -76,7 +85,8 @@ struct pdfs_ctx {
   pdfs::RoundState* st = nullptr;
   pdfs::RoundRecord* recs = nullptr;   // device, rec_cap records
   int rec_cap = 0;
-  pdfs::RoundState* h_st = nullptr;    // pinned
+  pdfs::RoundState* h_slots = nullptr; // pinned, kDepth states: one per chunk in flight
+  pdfs::RoundState* h_st = nullptr;    // the newest state read (one of h_slots)
   std::vector<int32_t> h_perm;
   std::string err;
   bool time_kernels = false;
@@ -84,8 +94,10 @@ struct pdfs_ctx {
   int chunk_items = 256;               // depth-3 candidates per DFS work item
   int n_cu = 256;                      // compute units of the device
   int seed_pairs_n = 256;              // bound mode: pairs expanded first
-  hipEvent_t ev[pdfs::kMaxChunk][5] = {};
-  hipEvent_t chunk_done = nullptr;
+  hipEvent_t ev[pdfs::kDepth][pdfs::kMaxChunk][5] = {};
+  hipEvent_t chunk_done[pdfs::kDepth] = {};
+  int chunk_rounds[pdfs::kDepth] = {};   // rounds of the chunk that uses each slot
+  int next_slot = 0;                     // slot of the next chunk (rotates across runs)
   // per-call accumulation of the timed launches
   int64_t kernel_ns[3] = {0, 0, 0};
   int32_t kernel_launches[3] = {0, 0, 0};
@@ -96,14 +108,15 @@ struct pdfs_ctx {
       graphs;
   size_t bytes = 0;                    // device bytes held (admission accounting)
   bool async_alloc = false;            // stream-ordered allocation (batched / served)
-  bool own_h_st = true;                // h_st allocated by the context
+  bool own_h_st = true;                // h_slots allocated by the context
 };
 
 namespace pdfs {
 
 int32_t ctx_fail(pdfs_ctx* c, int32_t code, const std::string& msg);
-// pdfs_create with two internal options: pinned_state (a caller-owned pinned
-// RoundState, or NULL) and stream-ordered allocation on opt->stream.
+// pdfs_create with two internal options: pinned_state (caller-owned pinned
+// memory for kDepth RoundStates, or NULL) and stream-ordered allocation on
+// opt->stream.
 int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out,
                    RoundState* pinned_state, bool async_alloc);
 void begin_stats(pdfs_ctx* c, pdfs_stats* st);
