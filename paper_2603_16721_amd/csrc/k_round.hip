@@ -189,7 +189,7 @@ __global__ void k_round_begin(Problem P, Work w) {
     st->incumbent = 0;
     st->n_seed = 0;
     st->seed_t = 0;
-    st->overflow = 0;
+    // overflow stays set for the rest of the run (cleared at run start)
     st->x_vis3 = st->x_vis4 = st->x_leaves = st->x_fp_leaves = 0;
   }
   for (int v = lane; v <= kMaxCount; v += 64) w.hist[v] = 0u;
@@ -366,6 +366,12 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
   if (st->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int h = P.h;
+  // a round whose lists overflowed is incomplete: it is not committed and the
+  // run stops (the host reports the overflow)
+  if (st->overflow) {
+    if (tid == 0) st->done = 1;
+    return;
+  }
   {
     // per-block counter rows of the kernels that ran this round; thread t
     // always reads field t % kTallyN, so the reads are contiguous
