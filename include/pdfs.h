@@ -207,6 +207,30 @@ int32_t pdfs_wsc_run(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alpha_
 const char *pdfs_strerror(int32_t status);
 const char *pdfs_last_error(const pdfs_ctx *ctx);
 
+/* ------------------------------------------------------- allocation-free round
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The round of pdfs_best_combo (same arguments, results and statistics, on a
+ * context made beforehand by pdfs_create, which does allocate) with every
+ * per-round buffer -- uncovered-sample list, active list, re-packed and
+ * unpacked rows, pair, work and item lists, argmax slots, counter rows, round
+ * state -- taken from one static device array of PDFS_NOALLOC_SCRATCH_BYTES
+ * instead of the context's workspace.  The library holds that array on every
+ * device it has created a context on, until the process ends.  The call makes
+ * no device allocation or free and calls no allocating library routine; it
+ * copies the mask in, launches on the context's stream and waits for the
+ * result.  Limits: h <= 4 (PDFS_ERR_UNSUPPORTED otherwise); a round whose
+ * fixed workspace (rows, unpacked rows and lists for the context's gene count
+ * and row width) exceeds the array is rejected with PDFS_ERR_UNSUPPORTED
+ * before any work; the pair and item lists take the rest of the array (up to
+ * every active pair), and a round whose non-empty pairs do not fit returns
+ * PDFS_ERR_OUT_OF_MEMORY.  pdfs_last_error() names the sizes.  Every call on
+ * a device shares that device's array (the round state, slots and counters are
+ * cleared by each call): calls that overlap on one device race. */
+#define PDFS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int32_t pdfs_best_combo_noalloc(pdfs_ctx *ctx, int32_t h, uint32_t alpha_p, uint32_t alpha_q,
+                                const uint64_t *uncovered, pdfs_combo *out, pdfs_stats *stats);
+
 /* Measurement support (not part of the method): the integer VALU rate the
  * device sustains for the depth-first kernels' per-word instruction pair
  * (an AND with a wave-uniform row word, then a popcount-accumulate), in

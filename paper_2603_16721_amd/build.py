@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["k_round.hip", "k_pairs.hip", "k_dfs.hip", "k_tri.hip", "k_deep.hip", "k_probe.hip",
-           "pdfs_api.cpp", "pdfs_batch.cpp"]
+           "pdfs_api.cpp", "pdfs_batch.cpp", "pdfs_noalloc.hip"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",

@@ -596,6 +596,14 @@ hipError_t launch_run_begin(const Problem& P, const Work& w, int max_rounds, hip
   return hipGetLastError();
 }
 
+hipError_t launch_zero_u32(void* p, size_t n32, hipStream_t s) {
+  if (n32 == 0) return hipSuccess;
+  const size_t blocks = (n32 + 255) / 256;
+  k_fill_u32<<<(int)(blocks < 1024 ? blocks : 1024), 256, 0, s>>>(static_cast<uint32_t*>(p), n32,
+                                                                  0u);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u(uint64_t* U, int wt, int n, hipStream_t s) {
   k_fill_u<<<(wt + 63) / 64, 64, 0, s>>>(U, wt, n);
   return hipGetLastError();

@@ -137,6 +137,10 @@ int32_t ensure_workspace(pdfs_ctx* c, int h) {
   return PDFS_OK;
 }
 
+}  // namespace
+
+namespace pdfs {
+
 Work make_work(pdfs_ctx* c, int w64, int target) {
   Work w;
   w.Ts = c->Ts; w.Ns = c->Ns; w.perm = c->perm; w.U = c->U; w.cols = c->cols; w.act = c->act;
@@ -166,8 +170,11 @@ Problem make_problem(const pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
 }
 
 // Enqueues one greedy round (every kernel returns at once if the run is
-// already done).  ev = the round's five timing events (used when timing).
-int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, hipEvent_t* ev) {
+// already done).  ev = the round's five timing events (used when timing);
+// two_phase: h = 4 under empty-prefix pruning lists long-stream prefixes for
+// the tile kernel (the lists must be in w).
+int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, hipEvent_t* ev,
+                      bool two_phase) {
   const int h = P.h;
   hipStream_t s = c->stream;
   const bool tk = c->time_kernels;
@@ -218,7 +225,7 @@ int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, hipEvent_t* 
         CK(c, launch_make_items(P, w, false, s));
         if (tk) CK(c, hipEventRecord(ev[2], s));
       }
-      if (c->two_phase) {
+      if (two_phase) {
         // the main DFS lists the prefixes with long depth-4 streams; they are
         // bucketed by c and expanded in tiles
         CK(c, launch_tri_begin(w, s));
@@ -236,19 +243,19 @@ int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, hipEvent_t* 
   // tiles, 2 = main DFS
   const int phases = h <= 2 ? 1
                      : (h >= 5 ? (c->prune_mode == PDFS_PRUNE_BOUND ? 6 : 4)
-                               : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 6 : 4));
+                               : (c->prune_mode == PDFS_PRUNE_BOUND || two_phase ? 6 : 4));
   // counter rows: 0 = pair table (h >= 2), 1 = seed DFS or depth-4 tiles,
   // 2 = main DFS
   // (h >= 5: the deep walk adds its counters directly)
   const int tallies = h == 1 ? 0
                       : (h == 2 || h >= 5
                              ? 1
-                             : (c->prune_mode == PDFS_PRUNE_BOUND || c->two_phase ? 7 : 5));
+                             : (c->prune_mode == PDFS_PRUNE_BOUND || two_phase ? 7 : 5));
   CK(c, launch_finish_round(P, w, phases, tallies, s));
   return PDFS_OK;
 }
 
-}  // namespace
+}  // namespace pdfs
 
 namespace pdfs {
 
@@ -267,7 +274,7 @@ static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int 
       hipGraph_t g = nullptr;
       hipGraphExec_t e = nullptr;
       CK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-      const int32_t rc = enqueue_round(c, P, w, c->ev[slot][0]);
+      const int32_t rc = enqueue_round(c, P, w, c->ev[slot][0], c->two_phase);
       hipGraph_t g2 = nullptr;
       const hipError_t ec = hipStreamEndCapture(c->stream, &g2);
       if (rc != PDFS_OK) {
@@ -284,7 +291,7 @@ static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int 
     return PDFS_OK;
   }
   for (int k = 0; k < chunk; ++k) {
-    const int32_t rc = enqueue_round(c, P, w, c->ev[slot][k]);
+    const int32_t rc = enqueue_round(c, P, w, c->ev[slot][k], c->two_phase);
     if (rc != PDFS_OK) return rc;
   }
   return PDFS_OK;
@@ -712,6 +719,7 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   } while (0)
   CKC(hipSetDevice(c->device));
   CKC(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  scratch_init(c->device);
   hipStream_t s = c->stream;
   const int G = m->G;
   if (c->time_kernels)
@@ -799,10 +807,10 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
     c->h_slots = pinned_state;
     c->own_h_st = false;
   } else {
-    CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_slots), kDepth * sizeof(RoundState),
-                      hipHostMallocDefault));
+    CKC(hipHostMalloc(reinterpret_cast<void**>(&c->h_slots), kPinnedBytes, hipHostMallocDefault));
   }
   c->h_st = &c->h_slots[0];
+  c->h_rec = reinterpret_cast<RoundRecord*>(c->h_slots + kDepth);
 
   CKC(hipMemsetAsync(c->st, 0, sizeof(RoundState), s));
   CKC(launch_clear_slots(c->slots, kSlotPhases * kSlotsPerPhase, s));

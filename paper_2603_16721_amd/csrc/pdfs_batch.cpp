@@ -300,7 +300,7 @@ struct pdfs_server {
   int device = 0;
   int prune_mode = PDFS_PRUNE_BOUND;
   std::vector<hipStream_t> streams;
-  std::vector<RoundState*> pinned_pool;   // kDepth pinned states per active slot
+  std::vector<RoundState*> pinned_pool;   // kPinnedBytes of pinned state per active slot
   size_t budget = 0, used = 0;
   int max_active = 8;
   std::mutex mu;
@@ -484,8 +484,8 @@ int32_t pdfs_server_create(const pdfs_options* opt, uint64_t hbm_budget_bytes, i
   }
   for (int k = 0; k < s->max_active; ++k) {
     RoundState* p = nullptr;
-    if (hipHostMalloc(reinterpret_cast<void**>(&p), kDepth * sizeof(RoundState),
-                      hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), kPinnedBytes, hipHostMallocDefault) !=
+        hipSuccess) {
       pdfs_server_destroy(s);
       return ctx_fail(nullptr, PDFS_ERR_OUT_OF_MEMORY, "pinned round-state pool");
     }

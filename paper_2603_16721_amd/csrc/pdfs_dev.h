@@ -225,6 +225,8 @@ hipError_t launch_dfs4_tiles(const Problem& P, const Work& w, hipStream_t s);
 hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, int tally_mask,
                                hipStream_t s);
 hipError_t launch_clear_slots(Slot* slots, int n, hipStream_t s);
+// n32 32-bit words at p set to zero by a fill kernel (no memset node)
+hipError_t launch_zero_u32(void* p, size_t n32, hipStream_t s);
 hipError_t launch_fill_u(uint64_t* U, int wt, int n, hipStream_t s);
 hipError_t launch_run_begin(const Problem& P, const Work& w, int max_rounds, hipStream_t s);
 

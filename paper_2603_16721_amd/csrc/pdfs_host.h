@@ -23,6 +23,10 @@ constexpr int kMaxChunk = 16;
 // the next is already queued, so the device does not wait for the host.
 constexpr int kDepth = 2;
 
+// Pinned host memory of a context: kDepth round states, then one round record
+// (the allocation-free entry point's read-back).
+constexpr size_t kPinnedBytes = kDepth * sizeof(RoundState) + sizeof(RoundRecord);
+
 // Progress of one greedy run on a context, advanced without blocking.  The
 // run's rounds go out in chunks; each chunk ends with a copy of the device
 // state into its pinned slot and an event.  The row width of a chunk comes
@@ -87,6 +91,7 @@ struct pdfs_ctx {
   int rec_cap = 0;
   pdfs::RoundState* h_slots = nullptr; // pinned, kDepth states: one per chunk in flight
   pdfs::RoundState* h_st = nullptr;    // the newest state read (one of h_slots)
+  pdfs::RoundRecord* h_rec = nullptr;  // pinned, after h_slots
   std::vector<int32_t> h_perm;
   std::string err;
   bool time_kernels = false;
@@ -115,7 +120,7 @@ namespace pdfs {
 
 int32_t ctx_fail(pdfs_ctx* c, int32_t code, const std::string& msg);
 // pdfs_create with two internal options: pinned_state (caller-owned pinned
-// memory for kDepth RoundStates, or NULL) and stream-ordered allocation on
+// memory of kPinnedBytes, or NULL) and stream-ordered allocation on
 // opt->stream.
 int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out,
                    RoundState* pinned_state, bool async_alloc);
@@ -133,11 +138,23 @@ int32_t run_poll(pdfs_ctx* c, bool wait, bool* ready, bool* done);
 // Blocking run: start + chunks until done.
 int32_t run_blocking(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int max_rounds,
                      int n_unc);
+// One round record as the ABI's pdfs_combo.
+void fill_combo(pdfs_combo* o, const RoundRecord& r, int h);
 // Copies up to cap round records of the finished run into out; returns rounds.
 int32_t run_records(pdfs_ctx* c, pdfs_combo* out, int32_t cap, int32_t* rounds);
 int32_t check_call(pdfs_ctx* c, int h, uint32_t p, uint32_t q);
 // Sets U from a host mask (NULL = all samples); returns |U| or -1.
 int32_t set_uncovered(pdfs_ctx* c, const uint64_t* mask);
+// Round workspace pointers and problem description of a context.
+Work make_work(pdfs_ctx* c, int w64, int target);
+Problem make_problem(const pdfs_ctx* c, int h, uint32_t p, uint32_t q);
+// Enqueues one round on c->stream with workspace w (see pdfs_api.cpp).
+int32_t enqueue_round(pdfs_ctx* c, const Problem& P, const Work& w, hipEvent_t* ev,
+                      bool two_phase);
+// Gets the static scratch array's device address on `device` once (the
+// allocation-free entry point's workspace); called by create_ctx with the
+// device current.
+void scratch_init(int device);
 // Device bytes a context of this shape will hold (admission control).
 size_t footprint_bytes(int G, int n_tumor, int n_normal, int nA_max, int h, int prune_mode);
 

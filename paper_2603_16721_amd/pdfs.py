@@ -72,7 +72,8 @@ EXPORTS = ["pdfs_create", "pdfs_destroy", "pdfs_set_prune_mode", "pdfs_best_comb
            "pdfs_batch_create", "pdfs_batch_run", "pdfs_batch_destroy",
            "pdfs_server_create", "pdfs_server_submit", "pdfs_server_poll", "pdfs_server_drain",
            "pdfs_server_destroy", "pdfs_measure_int_peak", "pdfs_batch_last_error",
-           "pdfs_server_last_error"]
+           "pdfs_server_last_error", "pdfs_best_combo_noalloc"]
+PDFS_NOALLOC_SCRATCH_BYTES = 64 << 20
 PDFS_OPT_GRAPHS = 2
 PDFS_OPT_AUTOTUNE = 4
 PDFS_OPT_TN_LITERAL = 8
@@ -94,6 +95,9 @@ def _load():
     L.pdfs_best_combo.argtypes = [P, i32, u32, u32, P, ctypes.POINTER(pdfs_combo),
                                   ctypes.POINTER(pdfs_stats)]
     L.pdfs_best_combo.restype = i32
+    L.pdfs_best_combo_noalloc.argtypes = [P, i32, u32, u32, P, ctypes.POINTER(pdfs_combo),
+                                          ctypes.POINTER(pdfs_stats)]
+    L.pdfs_best_combo_noalloc.restype = i32
     L.pdfs_wsc_run.argtypes = [P, i32, u32, u32, i32, i32, P, ctypes.POINTER(pdfs_combo), i32,
                                ctypes.POINTER(i32), P, ctypes.POINTER(pdfs_stats)]
     L.pdfs_wsc_run.restype = i32
@@ -234,6 +238,23 @@ def pdfs_best_combo(ctx, h, alpha_p, alpha_q, uncovered=None):
     return combo_dict(out), stats_dict(st, h)
 
 
+def pdfs_best_combo_noalloc(ctx, h, alpha_p, alpha_q, uncovered=None):
+    """The allocation-free round: returns (combo dict or None, stats dict)."""
+    out = pdfs_combo()
+    st = pdfs_stats()
+    u = None
+    if uncovered is not None:
+        u = np.ascontiguousarray(np.asarray(uncovered, dtype=np.uint64))
+    rc = lib.pdfs_best_combo_noalloc(ctx, h, alpha_p, alpha_q,
+                                     None if u is None else u.ctypes.data, ctypes.byref(out),
+                                     ctypes.byref(st))
+    if rc == PDFS_NO_COMBO:
+        return None, stats_dict(st, h)
+    if rc != PDFS_OK:
+        raise PdfsError(rc, lib.pdfs_last_error(ctx).decode())
+    return combo_dict(out), stats_dict(st, h)
+
+
 def pdfs_wsc_run(ctx, h, alpha_p, alpha_q, target_covered=0, max_rounds=0,
                  initial_uncovered=None, cap=4096, n_tumor=None):
     """Returns (list of combo dicts, stats dict, final uncovered mask or None)."""
@@ -289,6 +310,9 @@ class Solver:
 
     def best(self, h, p=1, q=10, uncovered=None):
         return pdfs_best_combo(self.ctx, h, p, q, uncovered)
+
+    def best_noalloc(self, h, p=1, q=10, uncovered=None):
+        return pdfs_best_combo_noalloc(self.ctx, h, p, q, uncovered)
 
     def wsc(self, h, p=1, q=10, target=0, max_rounds=0, initial_uncovered=None, cap=4096):
         return pdfs_wsc_run(self.ctx, h, p, q, target, max_rounds, initial_uncovered, cap,
