@@ -59,6 +59,20 @@ def words(n):
     return (n + 63) // 64
 
 
+def oracle_subsets_scored(workload):
+    """Sum over the rounds of the leaves Alg. 2 scores, from the oracle's stored
+    empty-mode solve of the workload (tests/golden/oracle_counters.json), or
+    None when none is stored."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_counters.json")
+    try:
+        with open(path) as f:
+            cases = json.load(f)["cases"]
+    except OSError:
+        return None
+    c = cases.get(f"{workload}_empty_all_rounds")
+    return None if c is None else int(c["nonempty"][c["h"]])
+
+
 def dfs_alg_ops(st, h, n_normal, depth3_ops_per_word=4):
     """Algorithmic integer lane-ops of the depth-first kernels for the work they
     were given.  A visited node of depth 3 or 4 costs one W-word AND plus a
@@ -273,6 +287,11 @@ def main():
 
     scored = stats[0]["nonempty"][h]
     assert all(s["nonempty"][h] == scored for s in stats)
+    # the same count from the oracle's stored walk of this solve (every round
+    # of Alg. 2 run on the CPU), when one is stored for the workload
+    oracle_scored = oracle_subsets_scored(inst.name)
+    if oracle_scored is not None:
+        assert scored == oracle_scored, (scored, oracle_scored)
     ms_per_step = 1e3 * elapsed / args.steps
     value = scored * args.steps / elapsed
 
@@ -413,7 +432,7 @@ def main():
         "config": {"workload": inst.name, "G": inst.G, "n_tumor": inst.n_tumor,
                    "n_normal": inst.n_normal, "h": h, "alpha": f"{p}/{q}",
                    "prune": "empty", "rounds": len(rounds), "subsets_scored_per_solve": scored,
-                   "seed": inst.seed},
+                   "oracle_subsets_scored_per_solve": oracle_scored, "seed": inst.seed},
         "wsc_solve_ms": {"empty": ms_per_step, "bound": bound_ms},
         "bound_matches_empty": same,
         # the same canonical subsets (the empty-mode leaves) over the bound-mode solve time

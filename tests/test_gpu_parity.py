@@ -240,6 +240,33 @@ def test_workload_h4_G20000_empty_round1_counters(pdfs):
     _counters_equal(stats, g, 4)
 
 
+def test_workload_h4_G20000_empty_all_rounds(pdfs):
+    """Full size, the paper's empty-only walk, the whole greedy solve (the
+    benchmark's step): all 133 rounds and the per-depth counts summed over
+    them equal the oracle's (stored; each round's empty-mode walk run on the
+    oracle in first-gene shares).  Then every round again on its own, from
+    the uncovered mask the oracle's sequence gives it, with that round's own
+    per-depth counts."""
+    I = synth.workload_h4_g20000()
+    T, N = I.packed()
+    g = _golden("h4_G20000_empty_all_rounds")
+    with pdfs.Solver(T, N, I.n_tumor, I.n_normal, "empty") as s:
+        got, stats, _ = s.wsc(4, 1, 10)
+        _same_rounds(got, g["rounds"])
+        _counters_equal(stats, g, 4)
+        U = cpu.full_mask(I.n_tumor, T.shape[1])
+        for r, rd in enumerate(g["rounds"]):
+            b, st = s.best(4, 1, 10, U)
+            _same_rounds([b], [rd])
+            for l in range(1, 5):
+                assert st["visited"][l] == g["per_round_visited"][r][l], (r, l)
+                assert st["nonempty"][l] == g["per_round_nonempty"][r][l], (r, l)
+            cov = U.copy()
+            for gene in rd["genes"]:
+                cov &= T[gene]
+            U = U & ~cov
+
+
 @pytest.mark.parametrize("key", ["h5_G5000_empty_round1", "h6_G5000_empty_round1"])
 @pytest.mark.parametrize("mode", ["empty", "bound"])
 def test_workload_h3_G5000_deeper_round1(pdfs, key, mode):

@@ -403,3 +403,35 @@ def test_best_share_partition(case, mode):
             for k in sums:
                 # depth 1 is the outer loop itself: its nodes are split, not repeated
                 assert sums[k] == whole.counters[k], (k, sums[k], whole.counters[k])
+
+
+def test_h4_G20000_stored_solve_consistent():
+    """The stored empty-mode solve of the G = 20000 workload (written by
+    tests/golden/make_goldens.py from first-gene shares of every round) is
+    pinned against things computed another way: its first round and that
+    round's per-depth counts equal the sequential whole-round walk stored
+    separately; every round passes the greedy invariants on a recount from
+    the raw bits; the per-round counts sum to the totals; and the solve ends
+    with every tumour sample covered by combinations that share an uncovered
+    sample no further."""
+    import json
+    with open(os.path.join(HERE, "golden", "oracle_counters.json")) as f:
+        cases = json.load(f)["cases"]
+    g = cases["h4_G20000_empty_all_rounds"]
+    r1 = cases["h4_G20000_empty_round1"]
+    assert g["rounds"][0] == r1["rounds"][0]
+    for l in range(1, 5):
+        assert g["per_round_visited"][0][l] == r1["visited"][l]
+        assert g["per_round_nonempty"][0][l] == r1["nonempty"][l]
+    for k in ("visited", "nonempty"):
+        tot = [sum(row[l] for row in g["per_round_" + k]) for l in range(len(g[k]))]
+        assert tot == g[k]
+    I = synth.workload_h4_g20000()
+    unc = np.ones(I.n_tumor, bool)
+    for rd in g["rounds"]:
+        unc = unc & ~recount(I.tumor, I.normal, rd["genes"], unc)[2]
+    _check_invariants(I, g["rounds"], mask_of_bits(unc), 4, 1, 10, True)
+    # exhaustive visits bound every round's count at each depth
+    for row in g["per_round_visited"]:
+        for l in range(1, 5):
+            assert row[l] <= math.comb(I.G, l)
