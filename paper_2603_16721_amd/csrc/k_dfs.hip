@@ -74,6 +74,230 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
   expand4<W, kBound>(P, w, st, y3, z3, znz, valid, a3, b3, c, c_first, best, tl, inc);
 }
 
+// The per-round values the depth-first walk of one instance reads.
+struct DfsView {
+  const unsigned long long* plist;   // phase 1: the seed list, 2: the work list
+  unsigned long long npairs;
+  const __attribute__((address_space(4))) Item* items;
+  int nA_all;
+  int c_long;       // c < c_long: at least w.long_stream depth-4 candidates
+  bool all_pre;     // exhaustive mode (h = 4): every depth-3 prefix is extended
+  bool list_long;   // two-phase depth 4: long-stream prefixes are listed
+};
+
+template <int H>
+__device__ __forceinline__ DfsView dfs_view(const Problem& P, const Work& w, const RoundState* st,
+                                            int phase) {
+  DfsView v;
+  v.plist = phase == 1 ? w.seed_pairs : w.work_pairs;
+  v.npairs = phase == 1 ? (st->n_seed < kSeedCap ? st->n_seed : kSeedCap) : st->n_work_pairs;
+  v.items = (const __attribute__((address_space(4))) Item*)w.items;
+  v.nA_all = uniform(st->nA);
+  v.c_long = v.nA_all - w.long_stream;
+  v.all_pre = H == 4 && P.mode == kPruneNone;
+  // Two-phase depth 4 (empty-prefix pruning, list allocated): prefixes whose
+  // candidate stream d > c is long are listed for the sorted tile kernel;
+  // the short ones are expanded here.
+  v.list_long = H == 4 && P.mode == kPruneEmpty && w.tri_cap > 0;
+  return v;
+}
+
+// One work item: 64 pairs (one per lane) x the depth-3 candidates [c_lo,
+// c_hi), each non-empty depth-3 prefix scored (h = 3), listed or queued and
+// expanded at depth 4 (h = 4).
+template <int H, int W64, bool kBound>
+__device__ __forceinline__ void dfs_item(const Problem& P, const Work& w, RoundState* st,
+                                         const DfsView& v, uint32_t it, uint32_t* q,
+                                         unsigned long long* sq, int& sn, Best& best, Tally& tl,
+                                         unsigned long long& inc, int lane) {
+  constexpr int W = 2 * W64;
+  constexpr bool kNarrow = W <= 8;
+  constexpr int KG = kNarrow ? 16 / W : 1;
+  const unsigned long long* __restrict__ plist = v.plist;
+  const unsigned long long npairs = v.npairs;
+  const auto items = v.items;
+  const int nA_all = v.nA_all;
+  const int c_long = v.c_long;
+  const bool all_pre = v.all_pre;
+  const bool list_long = v.list_long;
+  cu32* TA = (cu32*)w.TA;
+  cu32* NA = (cu32*)w.NA;
+  const int c_lo = uniform((int)items[it].c_lo);
+  const int c_hi = uniform((int)items[it].c_hi);
+  if (c_lo >= c_hi) return;   // never made by the item builder
+  const uint32_t batch = (uint32_t)uniform((int)items[it].batch);
+  const uint32_t first_chunk = (uint32_t)uniform((int)items[it].pad) & 1u;
+  const unsigned long long pi = (unsigned long long)batch * kPairBatch + lane;
+  bool valid = pi < npairs;
+  const unsigned long long e = valid ? plist[pi] : 0ull;
+  const int a = (int)(e & 0xffff);
+  const int b = (int)((e >> 16) & 0xffff);
+  const int ct = (int)((e >> 32) & 0xffff);
+  valid = valid && a < b && b < nA_all;   // list entries always satisfy this
+  if (kBound) {
+    inc = load_incumbent(st);
+    const bool drop = valid && dominated(P.p * ct + P.q * P.n_normal, a, b, inc);
+    if (first_chunk) {
+      tl.bp2 += __popcll(__ballot(drop));
+      if (valid && !drop) tl.vis3 += (unsigned long long)(P.G - H + 2 - w.act[b]);
+    }
+    valid = valid && !drop;
+  }
+  if (!__any(valid)) return;
+  uint32_t y2[W];
+  uint32_t z2[kMaxWN32];
+  const uint32_t vmask = valid ? ~0u : 0u;
+  const int ra = valid ? a : 0, rb = valid ? b : 0;   // in-range rows for idle lanes
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    y2[k] = TA[(size_t)ra * W + k] & TA[(size_t)rb * W + k] & vmask;
+#pragma unroll
+  for (int k = 0; k < kMaxWN32; ++k)
+    z2[k] = nrm_join(NA[(size_t)ra * kMaxWN32 + k], NA[(size_t)rb * kMaxWN32 + k],
+                     P.tn_literal) & vmask;
+  uint32_t znz = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxWN32; ++k) znz |= z2[k];
+  if (valid) {
+    const int lo = c_lo > b + 1 ? c_lo : b + 1;
+    if (c_hi > lo) tl.xv3 += (unsigned long long)(c_hi - lo);
+  }
+
+  int qn = 0;
+  // Non-empty depth-3 prefixes (lane, c) of candidate c, m = their lanes:
+  // scored (h = 3), or bound-tested and then listed or queued (h = 4).
+  // mq = the prefixes to extend: m, or every (lane, c) in exhaustive mode
+  auto on_hits = [&](int c, unsigned long long m, unsigned long long mq) {
+    bool hit = (m >> lane) & 1ull;
+    cu32* row = TA + (size_t)c * W;
+    tl.ne3 += __popcll(m);
+    if (all_pre) {
+      hit = (mq >> lane) & 1ull;
+      m = mq;
+    }
+    if (H == 3) {
+      int fp = 0;
+      const bool zn = znz != 0 || P.tn_literal;
+      if (__any(hit && zn)) {
+        if (hit && zn) {
+          fp = leaf_fp(z2, NA + (size_t)c * kMaxWN32, P.tn_literal);
+          tl.xfp++;
+        }
+      }
+      if (hit) {
+        const int tp = popc_and<W>(y2, row);
+        const int sc = P.p * tp + P.q * (P.n_normal - fp);
+        best.offer(sc, tp, fp, a, b, c, 0);
+        if (kBound) {
+          const unsigned long long key = leaf_key(sc, a, b);
+          if (key > inc) {
+            const unsigned long long old = atomicMax(&st->incumbent, key);
+            inc = old > key ? old : key;
+          }
+        }
+      }
+      return;
+    }
+    if (kBound) {
+      bool drop = false;
+      if (hit) {
+        const int cnt = popc_and<W>(y2, row);
+        drop = dominated(P.p * cnt + P.q * P.n_normal, a, b, inc);
+      }
+      tl.bp3 += __popcll(__ballot(drop));
+      hit = hit && !drop;
+      m = __ballot(hit);
+      if (m == 0) return;
+    }
+    if (list_long && c < c_long) {
+      const int sp = sn + __popcll(m & ((1ull << lane) - 1));
+      if (hit) sq[sp] = triple_entry(a, b, c);
+      sn += __popcll(m);
+      wave_lds_sync();
+      return;
+    }
+    const int pos = qn + __popcll(m & ((1ull << lane) - 1));
+    if (hit) q[pos] = (uint32_t)lane | ((uint32_t)c << 6);
+    qn += __popcll(m);
+    wave_lds_sync();
+  };
+  // Staged long-stream prefixes go out once kStage are waiting; every full
+  // wave of queued prefixes becomes a depth-4 pass.
+  auto drain = [&]() {
+    if (H != 4) return;
+    if (sn >= kStage) {
+      append_staged(w, st, sq, sn, lane);
+      sn = 0;
+    }
+    int off = 0;
+    while (qn - off >= kWave) {
+      depth4<W, kBound>(P, w, st, q + off, kWave, y2, z2, a, b, best, tl, inc, lane);
+      off += kWave;
+    }
+    if (off > 0) {
+      const int rest = qn - off;   // < kWave
+      const uint32_t moved = (lane < rest) ? q[off + lane] : 0u;
+      wave_lds_sync();
+      if (lane < rest) q[lane] = moved;
+      wave_lds_sync();
+      qn = rest;
+    }
+  };
+  if (!kNarrow) {
+    for (int c = c_lo; c < c_hi; ++c) {
+      const uint32_t acc = fold_nonempty<W>(y2, TA + (size_t)c * W);
+      const unsigned long long m = __ballot(valid && c > b && acc != 0);
+      const unsigned long long mq = all_pre ? __ballot(valid && c > b) : m;
+      if (mq == 0) continue;
+      on_hits(c, m, mq);
+      drain();
+    }
+  } else {
+    // rows past c_hi are loaded (inside the round's row allocation: at
+    // least 128 rows past the last active one) but never tested
+    const unsigned long long valid_m = __ballot(valid);
+    auto group = [&](int c0, const uint32_t (&rows)[KG][W]) {
+      unsigned long long m[KG], mq[KG];
+      unsigned long long any = 0;
+#pragma unroll
+      for (int j = 0; j < KG; ++j) {
+        const uint32_t acc = fold_nonempty_r<W>(y2, rows[j]);
+        const unsigned long long in = c0 + j < c_hi ? __ballot(c0 + j > b) & valid_m : 0ull;
+        m[j] = __ballot(acc != 0) & in;
+        mq[j] = all_pre ? in : m[j];
+        any |= mq[j];
+      }
+      if (any == 0) return;
+#pragma unroll
+      for (int j = 0; j < KG; ++j)
+        if (mq[j]) on_hits(c0 + j, m[j], mq[j]);
+      drain();
+    };
+    constexpr int kNoClamp = 0x7fffffff;
+    uint32_t rA[KG][W], rB[KG][W];
+    int c0 = c_lo;
+    load_rows<W, KG>(rA, TA, c0, kNoClamp);
+    for (;;) {
+      int cn = c0 + KG;
+      after_arrival<W, KG>(cn, rA);
+      load_rows<W, KG>(rB, TA, cn, kNoClamp);
+      group(c0, rA);
+      c0 += KG;
+      if (c0 >= c_hi) break;
+      cn = c0 + KG;
+      after_arrival<W, KG>(cn, rB);
+      load_rows<W, KG>(rA, TA, cn, kNoClamp);
+      group(c0, rB);
+      c0 += KG;
+      if (c0 >= c_hi) break;
+    }
+  }
+  if (H == 4 && qn > 0) {
+    depth4<W, kBound>(P, w, st, q, qn, y2, z2, a, b, best, tl, inc, lane);
+    qn = 0;
+  }
+}
+
 // kBound: bound pruning (Sec. III-E) compiled in; the other modes run the
 // instantiation without it.
 template <int H, int W64, bool kBound>
@@ -98,24 +322,10 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
   unsigned long long* sq = sbuf[wib];
   int sn = 0;
   // phase 1 expands the seed list, phase 2 the (filtered) work list
-  const unsigned long long* __restrict__ plist = phase == 1 ? w.seed_pairs : w.work_pairs;
-  const unsigned long long npairs =
-      phase == 1 ? (st->n_seed < kSeedCap ? st->n_seed : kSeedCap) : st->n_work_pairs;
+  const DfsView view = dfs_view<H>(P, w, st, phase);
   const unsigned long long nit = st->n_items;
   const uint32_t nitems = (uint32_t)uniform((int)(nit < w.item_cap ? nit : w.item_cap));
-  const int nA_all = uniform(st->nA);
-  // exhaustive mode (h = 4): every depth-3 prefix is extended, empty or not
-  const bool all_pre = H == 4 && P.mode == kPruneNone;
   if (blockIdx.x == 0 && threadIdx.x == 0 && nit > w.item_cap) st->overflow |= 1;
-  const __attribute__((address_space(4))) Item* items =
-      (const __attribute__((address_space(4))) Item*)w.items;
-  cu32* TA = (cu32*)w.TA;
-  cu32* NA = (cu32*)w.NA;
-  // Two-phase depth 4 (empty-prefix pruning, list allocated): prefixes whose
-  // candidate stream d > c is long are listed for the sorted tile kernel;
-  // the short ones are expanded here.
-  const bool list_long = H == 4 && P.mode == kPruneEmpty && w.tri_cap > 0;
-  const int c_long = nA_all - kLongStream;   // c < c_long: at least kLongStream candidates
 
   Best best;
   best.init();
@@ -144,180 +354,7 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
     }
     it = (uint32_t)uniform((int)it);
     if (it >= nitems) break;
-    const int c_lo = uniform((int)items[it].c_lo);
-    const int c_hi = uniform((int)items[it].c_hi);
-    if (c_lo >= c_hi) continue;   // never made by the item builder
-    const uint32_t batch = (uint32_t)uniform((int)items[it].batch);
-    const uint32_t first_chunk = (uint32_t)uniform((int)items[it].pad) & 1u;
-    const unsigned long long pi = (unsigned long long)batch * kPairBatch + lane;
-    bool valid = pi < npairs;
-    const unsigned long long e = valid ? plist[pi] : 0ull;
-    const int a = (int)(e & 0xffff);
-    const int b = (int)((e >> 16) & 0xffff);
-    const int ct = (int)((e >> 32) & 0xffff);
-    valid = valid && a < b && b < nA_all;   // list entries always satisfy this
-    if (kBound) {
-      inc = load_incumbent(st);
-      const bool drop = valid && dominated(P.p * ct + P.q * P.n_normal, a, b, inc);
-      if (first_chunk) {
-        tl.bp2 += __popcll(__ballot(drop));
-        if (valid && !drop) tl.vis3 += (unsigned long long)(P.G - H + 2 - w.act[b]);
-      }
-      valid = valid && !drop;
-    }
-    if (!__any(valid)) continue;
-    uint32_t y2[W];
-    uint32_t z2[kMaxWN32];
-    const uint32_t vmask = valid ? ~0u : 0u;
-    const int ra = valid ? a : 0, rb = valid ? b : 0;   // in-range rows for idle lanes
-#pragma unroll
-    for (int k = 0; k < W; ++k)
-      y2[k] = TA[(size_t)ra * W + k] & TA[(size_t)rb * W + k] & vmask;
-#pragma unroll
-    for (int k = 0; k < kMaxWN32; ++k)
-      z2[k] = nrm_join(NA[(size_t)ra * kMaxWN32 + k], NA[(size_t)rb * kMaxWN32 + k],
-                       P.tn_literal) & vmask;
-    uint32_t znz = 0;
-#pragma unroll
-    for (int k = 0; k < kMaxWN32; ++k) znz |= z2[k];
-    if (valid) {
-      const int lo = c_lo > b + 1 ? c_lo : b + 1;
-      if (c_hi > lo) tl.xv3 += (unsigned long long)(c_hi - lo);
-    }
-
-    int qn = 0;
-    // Non-empty depth-3 prefixes (lane, c) of candidate c, m = their lanes:
-    // scored (h = 3), or bound-tested and then listed or queued (h = 4).
-    // mq = the prefixes to extend: m, or every (lane, c) in exhaustive mode
-    auto on_hits = [&](int c, unsigned long long m, unsigned long long mq) {
-      bool hit = (m >> lane) & 1ull;
-      cu32* row = TA + (size_t)c * W;
-      tl.ne3 += __popcll(m);
-      if (all_pre) {
-        hit = (mq >> lane) & 1ull;
-        m = mq;
-      }
-      if (H == 3) {
-        int fp = 0;
-        const bool zn = znz != 0 || P.tn_literal;
-        if (__any(hit && zn)) {
-          if (hit && zn) {
-            fp = leaf_fp(z2, NA + (size_t)c * kMaxWN32, P.tn_literal);
-            tl.xfp++;
-          }
-        }
-        if (hit) {
-          const int tp = popc_and<W>(y2, row);
-          const int sc = P.p * tp + P.q * (P.n_normal - fp);
-          best.offer(sc, tp, fp, a, b, c, 0);
-          if (kBound) {
-            const unsigned long long key = leaf_key(sc, a, b);
-            if (key > inc) {
-              const unsigned long long old = atomicMax(&st->incumbent, key);
-              inc = old > key ? old : key;
-            }
-          }
-        }
-        return;
-      }
-      if (kBound) {
-        bool drop = false;
-        if (hit) {
-          const int cnt = popc_and<W>(y2, row);
-          drop = dominated(P.p * cnt + P.q * P.n_normal, a, b, inc);
-        }
-        tl.bp3 += __popcll(__ballot(drop));
-        hit = hit && !drop;
-        m = __ballot(hit);
-        if (m == 0) return;
-      }
-      if (list_long && c < c_long) {
-        const int sp = sn + __popcll(m & ((1ull << lane) - 1));
-        if (hit) sq[sp] = triple_entry(a, b, c);
-        sn += __popcll(m);
-        wave_lds_sync();
-        return;
-      }
-      const int pos = qn + __popcll(m & ((1ull << lane) - 1));
-      if (hit) q[pos] = (uint32_t)lane | ((uint32_t)c << 6);
-      qn += __popcll(m);
-      wave_lds_sync();
-    };
-    // Staged long-stream prefixes go out once kStage are waiting; every full
-    // wave of queued prefixes becomes a depth-4 pass.
-    auto drain = [&]() {
-      if (H != 4) return;
-      if (sn >= kStage) {
-        append_staged(w, st, sq, sn, lane);
-        sn = 0;
-      }
-      int off = 0;
-      while (qn - off >= kWave) {
-        depth4<W, kBound>(P, w, st, q + off, kWave, y2, z2, a, b, best, tl, inc, lane);
-        off += kWave;
-      }
-      if (off > 0) {
-        const int rest = qn - off;   // < kWave
-        const uint32_t moved = (lane < rest) ? q[off + lane] : 0u;
-        wave_lds_sync();
-        if (lane < rest) q[lane] = moved;
-        wave_lds_sync();
-        qn = rest;
-      }
-    };
-    if (!kNarrow) {
-      for (int c = c_lo; c < c_hi; ++c) {
-        const uint32_t acc = fold_nonempty<W>(y2, TA + (size_t)c * W);
-        const unsigned long long m = __ballot(valid && c > b && acc != 0);
-        const unsigned long long mq = all_pre ? __ballot(valid && c > b) : m;
-        if (mq == 0) continue;
-        on_hits(c, m, mq);
-        drain();
-      }
-    } else {
-      // rows past c_hi are loaded (inside the round's row allocation: at
-      // least 128 rows past the last active one) but never tested
-      const unsigned long long valid_m = __ballot(valid);
-      auto group = [&](int c0, const uint32_t (&rows)[KG][W]) {
-        unsigned long long m[KG], mq[KG];
-        unsigned long long any = 0;
-#pragma unroll
-        for (int j = 0; j < KG; ++j) {
-          const uint32_t acc = fold_nonempty_r<W>(y2, rows[j]);
-          const unsigned long long in = c0 + j < c_hi ? __ballot(c0 + j > b) & valid_m : 0ull;
-          m[j] = __ballot(acc != 0) & in;
-          mq[j] = all_pre ? in : m[j];
-          any |= mq[j];
-        }
-        if (any == 0) return;
-#pragma unroll
-        for (int j = 0; j < KG; ++j)
-          if (mq[j]) on_hits(c0 + j, m[j], mq[j]);
-        drain();
-      };
-      constexpr int kNoClamp = 0x7fffffff;
-      uint32_t rA[KG][W], rB[KG][W];
-      int c0 = c_lo;
-      load_rows<W, KG>(rA, TA, c0, kNoClamp);
-      for (;;) {
-        int cn = c0 + KG;
-        after_arrival<W, KG>(cn, rA);
-        load_rows<W, KG>(rB, TA, cn, kNoClamp);
-        group(c0, rA);
-        c0 += KG;
-        if (c0 >= c_hi) break;
-        cn = c0 + KG;
-        after_arrival<W, KG>(cn, rB);
-        load_rows<W, KG>(rA, TA, cn, kNoClamp);
-        group(c0, rB);
-        c0 += KG;
-        if (c0 >= c_hi) break;
-      }
-    }
-    if (H == 4 && qn > 0) {
-      depth4<W, kBound>(P, w, st, q, qn, y2, z2, a, b, best, tl, inc, lane);
-      qn = 0;
-    }
+    dfs_item<H, W64, kBound>(P, w, st, view, it, q, sq, sn, best, tl, inc, lane);
   }
   if (H == 4 && sn > 0) append_staged(w, st, sq, sn, lane);
 
@@ -351,11 +388,142 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
   }
 }
 
+// The depth-first step of a batched launch: one persistent grid drains the
+// shared queue of every live instance's work items (instance i owns the queue
+// positions [base[i], base[i+1])).  A wave works on one instance at a time;
+// its queue positions only grow, so when it moves past an instance it sends
+// that instance its staged prefixes, best leaf and counts, and never returns
+// to it within the launch.
+template <int H, int W64, bool kBound>
+__global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs_multi(
+    const BatchDesc* __restrict__ bd, BatchQueue* __restrict__ bq, int phase) {
+  constexpr int W = 2 * W64;
+  constexpr bool kNarrow = W <= 8;
+  constexpr int KG = kNarrow ? 16 / W : 1;
+  __shared__ uint32_t qbuf[kBlock / kWave][kWave * (KG + 1)];
+  __shared__ unsigned long long sbuf[kBlock / kWave][H == 4 ? kStage + KG * kWave : 1];
+  const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
+  uint32_t* q = qbuf[wib];
+  unsigned long long* sq = sbuf[wib];
+  int sn = 0;
+  const uint32_t total = (uint32_t)uniform((int)bq->total);
+  int cur = -1;
+  uint32_t lo = 0, hi = 0;
+  Problem P;
+  Work w;
+  RoundState* st = nullptr;
+  DfsView view;
+  Best best;
+  Tally tl;
+  unsigned long long inc = 0;
+  auto flush = [&]() {
+    if (H == 4 && sn > 0) {
+      append_staged(w, st, sq, sn, lane);
+      sn = 0;
+    }
+    Slot sl = empty_slot();
+    if (best.s >= 0) {
+      sl.s = best.s; sl.tp = best.tp; sl.fp = best.fp;
+      sl.idx[0] = best.idx(0); sl.idx[1] = best.idx(1); sl.idx[2] = best.idx(2);
+      sl.idx[3] = best.idx(3);
+    }
+    unsigned long long v[kTallyN] = {0};
+    if (lane == 0) {
+      v[kTNe3] = tl.ne3;
+      v[kTNe4] = H == 4 ? tl.ne4 : 0;
+      v[kTBp2] = tl.bp2;
+      v[kTBp3] = tl.bp3;
+      v[kTLeaves] = H == 3 ? tl.ne3 : tl.ne4;
+    }
+    v[kTVis3] = tl.vis3;
+    v[kTVis4] = H == 4 ? tl.vis4 : 0;
+    v[kTXv3] = tl.xv3;
+    v[kTXv4] = tl.xv4;
+    v[kTXfp] = tl.xfp;
+    wave_flush(w, st, phase, sl, v);
+  };
+  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
+  const uint32_t gw = blockIdx.x * (kBlock / kWave) + wib;
+  bool first = true;
+  for (;;) {
+    uint32_t g = total;
+    if (first) {
+      g = gw;
+      first = false;
+    } else if (lane == 0) {
+      const unsigned long long c =
+          __hip_atomic_load(&bq->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c + nwaves < total) g = (uint32_t)(nwaves + atomicAdd(&bq->cursor, 1ull));
+    }
+    g = (uint32_t)uniform((int)g);
+    if (g >= total) break;
+    if (g >= hi) {
+      if (cur >= 0) flush();
+      int i = cur + 1;   // g < total = base[n]: the scan stops at an instance below n
+      while ((uint32_t)uniform((int)bq->base[i + 1]) <= g) ++i;
+      cur = i;
+      lo = (uint32_t)uniform((int)bq->base[i]);
+      hi = (uint32_t)uniform((int)bq->base[i + 1]);
+      P = bd[i].P;
+      w = bd[i].w;
+      st = w.st;
+      view = dfs_view<H>(P, w, st, phase);
+      best.init();
+      tl.init();
+      inc = 0;
+    }
+    dfs_item<H, W64, kBound>(P, w, st, view, g - lo, q, sq, sn, best, tl, inc, lane);
+  }
+  if (cur >= 0) flush();
+}
+
+// One wave: the shared queue of a batched depth-first launch over the live
+// instances' work items (kind 0) or 64-prefix depth-4 tiles (kind 1), and the
+// phase's per-round log and counter row of every live instance cleared.
+__global__ __launch_bounds__(64) void k_batch_queue(const BatchDesc* __restrict__ bd, int n,
+                                                   BatchQueue* __restrict__ bq, int phase,
+                                                   int kind) {
+  const int lane = threadIdx.x;
+  unsigned long long cnt = 0;
+  if (lane < n) {
+    const Work& w = bd[lane].w;
+    RoundState* st = w.st;
+    if (!st->done) {
+      if (kind == 0) {
+        cnt = st->n_items;
+        if (cnt > w.item_cap) {
+          st->overflow |= 1;
+          cnt = w.item_cap;
+        }
+      } else {
+        const unsigned long long nt = st->n_tri < w.tri_cap ? st->n_tri : w.tri_cap;
+        cnt = (nt + kWave - 1) / kWave;
+      }
+      st->nlog[phase] = 0u;
+      for (int f = 0; f < kTallyN; ++f)
+        w.tallies[(size_t)phase * kPersistBlocks * kTallyN + f] = 0ull;
+    }
+  }
+  unsigned long long incl = cnt;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long x = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += x;
+  }
+  if (lane < n) bq->base[lane + 1] = (uint32_t)incl;
+  if (lane == 0) {
+    bq->base[0] = 0u;
+    bq->n = (uint32_t)n;
+    bq->cursor = 0ull;
+  }
+  if (lane == 63) bq->total = (uint32_t)incl;
+}
+
 // Work items: batches of kPairBatch consecutive list pairs, each batch's
 // depth-3 candidate range (min b + 1 .. amax[3]) cut into chunks.  One wave
 // handles 64 batches (lane j holds batch j's range) and reserves their items
 // with a single atomic.
-__global__ __launch_bounds__(256) void k_make_items(Problem P, Work w, int seed, int chunk0) {
+__device__ __forceinline__ void make_items_body(const Problem& P, const Work& w, int seed, int chunk0) {
   RoundState* st = w.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63;
@@ -366,7 +534,7 @@ __global__ __launch_bounds__(256) void k_make_items(Problem P, Work w, int seed,
   const unsigned long long nb = (np + kPairBatch - 1) / kPairBatch;
   const int amax3 = st->amax[3];
   // chunk length so that the item list cannot overflow
-  unsigned long long chunk = (unsigned long long)chunk0;
+  unsigned long long chunk = (unsigned long long)(chunk0 > 0 ? chunk0 : w.chunk);
   const unsigned long long room = w.item_cap > nb ? w.item_cap - nb : 1;
   const unsigned long long need = (nb * (unsigned long long)st->nA + room - 1) / room;
   if (need > chunk) chunk = need;
@@ -409,9 +577,17 @@ __global__ __launch_bounds__(256) void k_make_items(Problem P, Work w, int seed,
   }
 }
 
+__global__ __launch_bounds__(256) void k_make_items(Problem P, Work w, int seed, int chunk0) {
+  make_items_body(P, w, seed, chunk0);
+}
+
+__global__ __launch_bounds__(256) void k_make_items_m(const BatchDesc* __restrict__ bd, int seed, int chunk0) {
+  make_items_body(bd[blockIdx.y].P, bd[blockIdx.y].w, seed, chunk0);
+}
+
 // Bound mode: the pair list is final; the seed and work lists and the item
 // list start empty.
-__global__ void k_begin_bound_lists(Work w) {
+__device__ __forceinline__ void begin_bound_lists_body(const Work& w) {
   RoundState* st = w.st;
   if (st->done) return;
   if (st->n_pairs > w.pair_cap) { st->n_pairs = w.pair_cap; st->overflow = 1; }
@@ -421,8 +597,16 @@ __global__ void k_begin_bound_lists(Work w) {
   st->cursor = 0;
 }
 
+__global__ void k_begin_bound_lists(Work w) {
+  begin_bound_lists_body(w);
+}
+
+__global__ void k_begin_bound_lists_m(const BatchDesc* __restrict__ bd) {
+  begin_bound_lists_body(bd[blockIdx.y].w);
+}
+
 // Empty-only mode: every emitted pair is expanded.
-__global__ void k_use_all_pairs(Work w) {
+__device__ __forceinline__ void use_all_pairs_body(const Work& w) {
   RoundState* st = w.st;
   if (st->done) return;
   unsigned long long n = st->n_pairs;
@@ -433,9 +617,17 @@ __global__ void k_use_all_pairs(Work w) {
   st->cursor = 0;
 }
 
+__global__ void k_use_all_pairs(Work w) {
+  use_all_pairs_body(w);
+}
+
+__global__ void k_use_all_pairs_m(const BatchDesc* __restrict__ bd) {
+  use_all_pairs_body(bd[blockIdx.y].w);
+}
+
 // ---- bound mode: seed selection and pair filtering -------------------------
 // Histogram of the pair counts (C_T) of all emitted pairs.
-__global__ __launch_bounds__(256) void k_pair_hist(Work w) {
+__device__ __forceinline__ void pair_hist_body(const Work& w) {
   __shared__ uint32_t h[kMaxCount + 1];
   if (w.st->done) return;
   for (int v = threadIdx.x; v <= kMaxCount; v += blockDim.x) h[v] = 0u;
@@ -449,6 +641,14 @@ __global__ __launch_bounds__(256) void k_pair_hist(Work w) {
   __syncthreads();
   for (int v = threadIdx.x; v <= kMaxCount; v += blockDim.x)
     if (h[v]) atomicAdd(&w.hist[v], h[v]);
+}
+
+__global__ __launch_bounds__(256) void k_pair_hist(Work w) {
+  pair_hist_body(w);
+}
+
+__global__ __launch_bounds__(256) void k_pair_hist_m(const BatchDesc* __restrict__ bd) {
+  pair_hist_body(bd[blockIdx.y].w);
 }
 
 // Threshold t: the largest count such that at least `want` pairs reach it (1
@@ -487,7 +687,7 @@ __device__ int seed_threshold(const uint32_t* __restrict__ hist, int want) {
 
 // Pairs with count >= t go to the seed list (up to kSeedCap) and are marked
 // (bit 63) in the full list so that the main phase skips them.
-__global__ __launch_bounds__(256) void k_seed_select(Work w) {
+__device__ __forceinline__ void seed_select_body(const Work& w) {
   RoundState* st = w.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63;
@@ -513,10 +713,18 @@ __global__ __launch_bounds__(256) void k_seed_select(Work w) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_seed_select(Work w) {
+  seed_select_body(w);
+}
+
+__global__ __launch_bounds__(256) void k_seed_select_m(const BatchDesc* __restrict__ bd) {
+  seed_select_body(bd[blockIdx.y].w);
+}
+
 // Main-phase list: every unmarked pair whose bound can still reach the
 // incumbent found by the seed phase.  Waves append their survivors in list
 // order, so batches keep the locality of the pair table's tiles.
-__global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
+__device__ __forceinline__ void filter_pairs_body(const Problem& P, const Work& w) {
   RoundState* st = w.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63;
@@ -554,6 +762,14 @@ __global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
   if (lane == 0 && dropped) atomicAdd(&bsum, dropped);
   __syncthreads();
   if (threadIdx.x == 0 && bsum) atomicAdd(&st->cnt.bound_pruned[2], bsum);
+}
+
+__global__ __launch_bounds__(256) void k_filter_pairs(Problem P, Work w) {
+  filter_pairs_body(P, w);
+}
+
+__global__ __launch_bounds__(256) void k_filter_pairs_m(const BatchDesc* __restrict__ bd) {
+  filter_pairs_body(bd[blockIdx.y].P, bd[blockIdx.y].w);
 }
 
 // Blocks of one DFS instantiation resident per compute unit (register use
@@ -603,6 +819,42 @@ hipError_t dispatch(const Problem& P, const Work& w, int phase, hipStream_t s) {
 
 }  // namespace
 
+// ---- batched launches
+template <int H, int W64, bool kBound>
+hipError_t launch_multi_mode(const BatchDesc* bd, BatchQueue* bq, int phase, int n_cu,
+                             hipStream_t s) {
+  static const int per_cu = [] {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &v, reinterpret_cast<const void*>(&k_dfs_multi<H, W64, kBound>), kBlock, 0) !=
+            hipSuccess ||
+        v < 1)
+      v = 1;
+    return v;
+  }();
+  int blocks = per_cu * (n_cu > 0 ? n_cu : 1);
+  if (blocks > kPersistBlocks) blocks = kPersistBlocks;
+  k_dfs_multi<H, W64, kBound><<<blocks, kBlock, 0, s>>>(bd, bq, phase);
+  return hipGetLastError();
+}
+
+template <int H>
+hipError_t dispatch_multi(int w64, bool bound, const BatchDesc* bd, BatchQueue* bq, int phase,
+                          int n_cu, hipStream_t s) {
+  switch (w64) {
+#define PDFS_CASE(n)                                                                   \
+  case n:                                                                              \
+    return bound ? launch_multi_mode<H, n, true>(bd, bq, phase, n_cu, s)               \
+                 : launch_multi_mode<H, n, false>(bd, bq, phase, n_cu, s);
+    PDFS_CASE(1) PDFS_CASE(2) PDFS_CASE(3) PDFS_CASE(4) PDFS_CASE(5) PDFS_CASE(6)
+    PDFS_CASE(7) PDFS_CASE(8) PDFS_CASE(10) PDFS_CASE(12) PDFS_CASE(14) PDFS_CASE(16)
+    PDFS_CASE(18) PDFS_CASE(20)
+#undef PDFS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 // Row width (64-bit words) the DFS kernels are built for: the smallest
 // instantiated width that holds n words.
 int dfs_row_words(int n) {
@@ -632,6 +884,42 @@ hipError_t launch_seed_select(const Problem& P, const Work& w, hipStream_t s) {
 
 hipError_t launch_filter_pairs(const Problem& P, const Work& w, hipStream_t s) {
   k_filter_pairs<<<kPersistBlocks / 2, kBlock, 0, s>>>(P, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_queue(const BatchDesc* bd, int n, BatchQueue* bq, int phase, int kind,
+                              hipStream_t s) {
+  k_batch_queue<<<1, 64, 0, s>>>(bd, n, bq, phase, kind);
+  return hipGetLastError();
+}
+
+hipError_t launch_dfs_m(int h, int w64, bool bound, const BatchDesc* bd, BatchQueue* bq,
+                        int phase, int n_cu, hipStream_t s) {
+  if (h == 3) return dispatch_multi<3>(w64, bound, bd, bq, phase, n_cu, s);
+  if (h == 4) return dispatch_multi<4>(w64, bound, bd, bq, phase, n_cu, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_make_items_m(const BatchDesc* bd, int n, bool seed, hipStream_t s) {
+  // seed phase: 32 candidates per item; main phase: each instance's own chunk
+  k_make_items_m<<<dim3(kPersistBlocks / 4, n), kBlock, 0, s>>>(bd, seed ? 1 : 0, seed ? 32 : -1);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_select_m(const BatchDesc* bd, int n, hipStream_t s) {
+  k_begin_bound_lists_m<<<dim3(1, n), 1, 0, s>>>(bd);
+  k_pair_hist_m<<<dim3(64, n), 256, 0, s>>>(bd);
+  k_seed_select_m<<<dim3(kPersistBlocks / 4, n), kBlock, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_pairs_m(const BatchDesc* bd, int n, hipStream_t s) {
+  k_filter_pairs_m<<<dim3(kPersistBlocks / 4, n), kBlock, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_use_all_pairs_m(const BatchDesc* bd, int n, hipStream_t s) {
+  k_use_all_pairs_m<<<dim3(1, n), 1, 0, s>>>(bd);
   return hipGetLastError();
 }
 

@@ -107,7 +107,7 @@ __device__ __forceinline__ void mm_loop(const int8_t* __restrict__ M, int kpad, 
 }
 
 template <bool kH2>
-__global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
+__device__ __forceinline__ void pairs_body(const Problem& P, const Work& w) {
   __shared__ __attribute__((aligned(16))) int8_t sA[kBT * kLds];
   __shared__ __attribute__((aligned(16))) int8_t sB[kBT * kLds];
   __shared__ int wsum[4];
@@ -236,7 +236,24 @@ __global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
   }
 }
 
+template <bool kH2>
+__global__ __launch_bounds__(256) void k_pairs(Problem P, Work w) {
+  pairs_body<kH2>(P, w);
+}
+
+template <bool kH2>
+__global__ __launch_bounds__(256) void k_pairs_m(const BatchDesc* __restrict__ bd) {
+  pairs_body<kH2>(bd[blockIdx.y].P, bd[blockIdx.y].w);
+}
+
 }  // namespace
+
+// Batched launches (h >= 3): 256 blocks per instance; the counter rows of
+// blocks 256.. stay as cleared at the start of the batched run.
+hipError_t launch_pairs_m(const BatchDesc* bd, int n, hipStream_t s) {
+  k_pairs_m<false><<<dim3(kPersistBlocks / 4, n), kBlock, 0, s>>>(bd);
+  return hipGetLastError();
+}
 
 hipError_t launch_pairs(const Problem& P, const Work& w, hipStream_t s) {
   if (P.h == 2)

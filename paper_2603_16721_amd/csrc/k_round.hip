@@ -156,7 +156,7 @@ __global__ void k_fill_u(uint64_t* U, int wt, int n) {
 
 // ------------------------------------------------------------- round begin
 // One block of 64 threads: uncovered sample list and state reset.
-__global__ void k_round_begin(Problem P, Work w) {
+__device__ __forceinline__ void round_begin_body(const Problem& P, const Work& w) {
   RoundState* st = w.st;
   if (st->done) return;   // rounds queued past the stop are no-ops
   const int lane = threadIdx.x;
@@ -201,8 +201,16 @@ __global__ void k_round_begin(Problem P, Work w) {
   }
 }
 
+__global__ void k_round_begin(Problem P, Work w) {
+  round_begin_body(P, w);
+}
+
+__global__ void k_round_begin_m(const BatchDesc* __restrict__ bd) {
+  round_begin_body(bd[blockIdx.y].P, bd[blockIdx.y].w);
+}
+
 // ------------------------------------------------------------- active genes
-__global__ void k_active_flags(Problem P, Work w) {
+__device__ __forceinline__ void active_flags_body(const Problem& P, const Work& w) {
   if (w.st->done) return;
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= P.G) return;
@@ -213,10 +221,18 @@ __global__ void k_active_flags(Problem P, Work w) {
   w.flags[g] = acc != 0 ? 1 : (P.mode == kPruneNone ? 2 : 0);
 }
 
+__global__ void k_active_flags(Problem P, Work w) {
+  active_flags_body(P, w);
+}
+
+__global__ void k_active_flags_m(const BatchDesc* __restrict__ bd) {
+  active_flags_body(bd[blockIdx.y].P, bd[blockIdx.y].w);
+}
+
 // One block of 1024 threads: ordered compaction of the active flags, the
 // per-depth limits amax[l] and the depth-1/2 counters (Alg. 2 loop bounds:
 // depth l takes sorted indices up to G-h+l-1).
-__global__ __launch_bounds__(1024) void k_active_scan(Problem P, Work w) {
+__device__ __forceinline__ void active_scan_body(const Problem& P, const Work& w) {
   __shared__ int wsum[16];
   __shared__ unsigned long long vsum[16];
   __shared__ int nsum[16];
@@ -281,11 +297,18 @@ __global__ __launch_bounds__(1024) void k_active_scan(Problem P, Work w) {
   }
 }
 
+__global__ __launch_bounds__(1024) void k_active_scan(Problem P, Work w) {
+  active_scan_body(P, w);
+}
+
+__global__ __launch_bounds__(1024) void k_active_scan_m(const BatchDesc* __restrict__ bd) {
+  active_scan_body(bd[blockIdx.y].P, bd[blockIdx.y].w);
+}
+
 // One wave per active gene: the row over the uncovered columns (the paper's
 // DelCols done physically), the normal row, and optionally 0/1 bytes for the
 // int8 MFMA pair table.
-__global__ __launch_bounds__(256) void k_gather_active(Problem P, Work w, int unpack_t,
-                                                       int unpack_n) {
+__device__ __forceinline__ void gather_active_body(const Problem& P, const Work& w, int unpack_t, int unpack_n) {
   const RoundState* st = w.st;
   if (st->done) return;
   const int nA = st->nA, n_unc = st->n_unc;
@@ -322,6 +345,15 @@ __global__ __launch_bounds__(256) void k_gather_active(Problem P, Work w, int un
   }
 }
 
+__global__ __launch_bounds__(256) void k_gather_active(Problem P, Work w, int unpack_t,
+                                                       int unpack_n) {
+  gather_active_body(P, w, unpack_t, unpack_n);
+}
+
+__global__ __launch_bounds__(256) void k_gather_active_m(const BatchDesc* __restrict__ bd, int unpack_t, int unpack_n) {
+  gather_active_body(bd[blockIdx.y].P, bd[blockIdx.y].w, unpack_t, unpack_n);
+}
+
 // ------------------------------------------------------------- h = 1
 // Every active gene is a leaf: S = p*|T_g & U| + q*(N_n - |N_g|).
 __global__ __launch_bounds__(256) void k_h1(Problem P, Work w) {
@@ -354,8 +386,16 @@ __global__ void k_clear_slots(Slot* slots, int n) {
 // ------------------------------------------------------------- finish
 // One block: argmax over the slots of the phases used this round, the round
 // record, and the cover update U <- U & ~(U & T_g1 & ... & T_gh).
-__global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int phase_mask,
-                                                      int tally_mask) {
+__device__ __forceinline__ void finish_round_body(const Problem& P, const Work& w, int phase_mask,
+                                                  int tally_mask) {
+  // batched launches (h >= 3) pass -1: the instance's own phases -- the seed
+  // walk (bound mode) or the depth-4 tiles (two-phase) in phase 1, the main
+  // walk in phase 2, the pair table's counts in row 0
+  if (phase_mask < 0) {
+    const bool two = P.mode == kPruneBound || (P.h == 4 && P.mode == kPruneEmpty && w.tri_cap > 0);
+    phase_mask = two ? 6 : 4;
+    tally_mask = two ? 7 : 5;
+  }
   __shared__ Slot red[16];
   __shared__ int s_found;
   __shared__ Slot s_best;
@@ -417,8 +457,13 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
   for (int i = 0; i < kMaxH; ++i) b.idx[i] = 0;
   for (int ph = 0; ph < kSlotPhases; ++ph) {
     if (!((phase_mask >> ph) & 1)) continue;
-    for (int i = tid; i < kSlotsPerPhase; i += 1024) {
-      Slot c = w.slots[(size_t)ph * kSlotsPerPhase + i];
+    // a context's own launches leave one slot per block; a batched launch
+    // leaves the log of the waves that worked on this instance
+    const Slot* src = w.slot_log ? w.slot_log + (size_t)ph * kLogCap
+                                 : w.slots + (size_t)ph * kSlotsPerPhase;
+    const int n = w.slot_log ? min((int)st->nlog[ph], kLogCap) : kSlotsPerPhase;
+    for (int i = tid; i < n; i += 1024) {
+      Slot c = src[i];
       if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less(c.idx, b.idx, h))) b = c;
     }
   }
@@ -513,9 +558,18 @@ __global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int ph
   }
 }
 
+__global__ __launch_bounds__(1024) void k_finish_round(Problem P, Work w, int phase_mask,
+                                                      int tally_mask) {
+  finish_round_body(P, w, phase_mask, tally_mask);
+}
+
+__global__ __launch_bounds__(1024) void k_finish_round_m(const BatchDesc* __restrict__ bd, int phase_mask, int tally_mask) {
+  finish_round_body(bd[blockIdx.y].P, bd[blockIdx.y].w, phase_mask, tally_mask);
+}
+
 // Whole-run state: nothing done yet, totals cleared, the covered count of the
 // starting mask.
-__global__ void k_run_begin(Problem P, Work w, int max_rounds) {
+__device__ __forceinline__ void run_begin_body(const Problem& P, const Work& w, int max_rounds) {
   RoundState* st = w.st;
   const int lane = threadIdx.x;
   int c = 0;
@@ -541,6 +595,14 @@ __global__ void k_run_begin(Problem P, Work w, int max_rounds) {
     st->tot.nonempty[l] = 0;
     st->tot.bound_pruned[l] = 0;
   }
+}
+
+__global__ void k_run_begin(Problem P, Work w, int max_rounds) {
+  run_begin_body(P, w, max_rounds);
+}
+
+__global__ void k_run_begin_m(const BatchDesc* __restrict__ bd, int max_rounds) {
+  run_begin_body(bd[blockIdx.y].P, bd[blockIdx.y].w, max_rounds);
 }
 
 }  // namespace
@@ -636,6 +698,35 @@ hipError_t launch_h1(const Problem& P, const Work& w, hipStream_t s) {
 hipError_t launch_finish_round(const Problem& P, const Work& w, int phase_mask, int tally_mask,
                                hipStream_t s) {
   k_finish_round<<<1, 1024, 0, s>>>(P, w, phase_mask, tally_mask);
+  return hipGetLastError();
+}
+
+// ---- batched launches: one block row per instance (blockIdx.y)
+hipError_t launch_run_begin_m(const BatchDesc* bd, int n, int max_rounds, hipStream_t s) {
+  k_run_begin_m<<<dim3(1, n), 64, 0, s>>>(bd, max_rounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_begin_m(const BatchDesc* bd, int n, hipStream_t s) {
+  k_round_begin_m<<<dim3(1, n), 64, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_active_m(const BatchDesc* bd, int n, int max_G, hipStream_t s) {
+  k_active_flags_m<<<dim3((max_G + 255) / 256, n), 256, 0, s>>>(bd);
+  k_active_scan_m<<<dim3(1, n), 1024, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_active_m(const BatchDesc* bd, int n, int max_G, hipStream_t s) {
+  int blocks = (max_G + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  k_gather_active_m<<<dim3(blocks, n), 256, 0, s>>>(bd, 1, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_round_m(const BatchDesc* bd, int n, hipStream_t s) {
+  k_finish_round_m<<<dim3(1, n), 1024, 0, s>>>(bd, -1, -1);
   return hipGetLastError();
 }
 

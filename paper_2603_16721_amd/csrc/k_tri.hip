@@ -9,7 +9,8 @@
 // the dense ones at its end -- where most prefixes are.  So the level is
 // split by stream length:
 //
-//   * prefixes with at least kLongStream candidates are listed by the main
+//   * prefixes with at least long_stream candidates (a per-context setting,
+//     384 by default) are listed by the main
 //     DFS kernel (and counted per c), bucketed by c with a counting sort and
 //     expanded here in tiles of 64 consecutive entries: every lane busy, all
 //     lanes of a tile with (nearly) the same c;
@@ -39,16 +40,25 @@ __device__ __forceinline__ void clear_absent_blocks(const Work& w, int phase, bo
 }
 
 // Per-round reset: empty list, zero per-c counts.
-__global__ void k_tri_begin(Work w) {
+__device__ __forceinline__ void tri_begin_body(const Work& w) {
   RoundState* st = w.st;
   if (st->done) return;
   const int nA = st->nA;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nA; i += gridDim.x * blockDim.x)
-    w.c_hist[i] = 0u;
+  if (w.tri_cap > 0)   // (a batched launch also reaches instances without lists)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nA; i += gridDim.x * blockDim.x)
+      w.c_hist[i] = 0u;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->n_tri = 0;
     st->tri_cursor = 0;
   }
+}
+
+__global__ void k_tri_begin(Work w) {
+  tri_begin_body(w);
+}
+
+__global__ void k_tri_begin_m(const BatchDesc* __restrict__ bd) {
+  tri_begin_body(bd[blockIdx.y].w);
 }
 
 // Sizing pass: counts the non-empty depth-3 prefixes with long candidate
@@ -65,7 +75,7 @@ __global__ __launch_bounds__(256) void k_count_long(Problem P, Work w) {
   const unsigned long long nit = st->n_items;
   const uint32_t nitems = (uint32_t)uniform((int)(nit < w.item_cap ? nit : w.item_cap));
   const int nA_all = uniform(st->nA);
-  const int c_long = nA_all - kLongStream;
+  const int c_long = nA_all - w.long_stream;
   const __attribute__((address_space(4))) Item* items =
       (const __attribute__((address_space(4))) Item*)w.items;
   cu32* TA = (cu32*)w.TA;
@@ -97,10 +107,10 @@ __global__ __launch_bounds__(256) void k_count_long(Problem P, Work w) {
 }
 
 // Exclusive prefix of the per-c counts, in place (one block).
-__global__ __launch_bounds__(1024) void k_scan_c(Work w) {
+__device__ __forceinline__ void scan_c_body(const Work& w) {
   __shared__ unsigned long long part[1024];
   RoundState* st = w.st;
-  if (st->done) return;
+  if (st->done || w.tri_cap == 0) return;
   const int nA = st->nA;
   const int tid = threadIdx.x;
   if (tid == 0 && st->n_tri > w.tri_cap) st->overflow |= 1;
@@ -125,11 +135,19 @@ __global__ __launch_bounds__(1024) void k_scan_c(Work w) {
   }
 }
 
+__global__ __launch_bounds__(1024) void k_scan_c(Work w) {
+  scan_c_body(w);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_c_m(const BatchDesc* __restrict__ bd) {
+  scan_c_body(bd[blockIdx.y].w);
+}
+
 // Scatter into c buckets: each run of equal c among 64 consecutive entries
 // takes its slots with one atomic on the bucket's cursor.
-__global__ __launch_bounds__(256) void k_scatter_c(Work w) {
+__device__ __forceinline__ void scatter_c_body(const Work& w) {
   RoundState* st = w.st;
-  if (st->done) return;
+  if (st->done || w.tri_cap == 0) return;
   const int lane = threadIdx.x & 63;
   const unsigned long long n = st->n_tri < w.tri_cap ? st->n_tri : w.tri_cap;
   for (unsigned long long base = (unsigned long long)(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6)) * kWave;
@@ -156,6 +174,14 @@ __global__ __launch_bounds__(256) void k_scatter_c(Work w) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_scatter_c(Work w) {
+  scatter_c_body(w);
+}
+
+__global__ __launch_bounds__(256) void k_scatter_c_m(const BatchDesc* __restrict__ bd) {
+  scatter_c_body(bd[blockIdx.y].w);
+}
+
 // Depth-4 expansion of the sorted list, 64 consecutive prefixes per wave.
 // Tiles go out in list order (ascending c: the longest streams first); a
 // wave takes several consecutive tiles per cursor step when their streams
@@ -169,6 +195,49 @@ constexpr int kMaxGrab = 16;
 #define PDFS_TILE3_MAX_W64 16
 #endif
 
+// Depth-4 expansion of tile `it`: the listed prefixes it*64 .. it*64+63 (n
+// listed in all), one per lane.
+template <int W64>
+__device__ __forceinline__ void tile_item(const Problem& P, const Work& w, RoundState* st,
+                                          uint32_t it, unsigned long long n, int nA, Best& best,
+                                          Tally& tl, unsigned long long& inc, int lane) {
+  constexpr int W = 2 * W64;
+  cu32* TA = (cu32*)w.TA;
+  cu32* NA = (cu32*)w.NA;
+  const unsigned long long t0 = (unsigned long long)it * kWave;
+  bool valid = t0 + lane < n;
+  const unsigned long long e = w.tri_s[valid ? t0 + lane : t0];
+  int a3 = (int)(e & 0xffff);
+  int b3 = (int)((e >> 16) & 0xffff);
+  int c = (int)((e >> 32) & 0xffff);
+  // listed entries always satisfy a < b < c < nA; anything else marks the
+  // round corrupt and is never used as a row index
+  if (valid && !(a3 < b3 && b3 < c && c < nA)) {
+    st->overflow |= 2;
+    valid = false;
+  }
+  if (!valid) a3 = b3 = c = 0;
+  const uint32_t vmask = valid ? ~0u : 0u;
+  uint32_t y3[W];
+  uint32_t z3[kMaxWN32];
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    y3[k] = TA[(size_t)a3 * W + k] & TA[(size_t)b3 * W + k] & TA[(size_t)c * W + k] & vmask;
+  uint32_t znz = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxWN32; ++k) {
+    z3[k] = nrm_join(nrm_join(NA[(size_t)a3 * kMaxWN32 + k], NA[(size_t)b3 * kMaxWN32 + k],
+                              P.tn_literal),
+                     NA[(size_t)c * kMaxWN32 + k], P.tn_literal) & vmask;
+    znz |= z3[k];
+  }
+  // visited at depth 4 below the prefix: sorted indices in (idx(c), G-1]
+  if (valid) tl.vis4 += (unsigned long long)(P.G - 1 - w.act[c]);
+  int cmin = valid ? c : 0x7fffffff;
+  for (int o = 32; o > 0; o >>= 1) cmin = min(cmin, __shfl_xor(cmin, o, 64));
+  expand4<W>(P, w, st, y3, z3, znz, valid, a3, b3, c, uniform(cmin), best, tl, inc);
+}
+
 template <int W64>
 __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_dfs4_tiles(Problem P,
                                                                                         Work w) {
@@ -180,8 +249,6 @@ __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_df
   const unsigned long long n = st->n_tri < w.tri_cap ? st->n_tri : w.tri_cap;
   const uint32_t ntiles = (uint32_t)((n + kWave - 1) / kWave);
   const int nA = uniform(st->nA);
-  cu32* TA = (cu32*)w.TA;
-  cu32* NA = (cu32*)w.NA;
 
   Best best;
   best.init();
@@ -212,38 +279,7 @@ __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_df
     }
     if (t_next >= ntiles) break;
     const uint32_t it = t_next++;
-    const unsigned long long t0 = (unsigned long long)it * kWave;
-    bool valid = t0 + lane < n;
-    const unsigned long long e = w.tri_s[valid ? t0 + lane : t0];
-    int a3 = (int)(e & 0xffff);
-    int b3 = (int)((e >> 16) & 0xffff);
-    int c = (int)((e >> 32) & 0xffff);
-    // listed entries always satisfy a < b < c < nA; anything else marks the
-    // round corrupt and is never used as a row index
-    if (valid && !(a3 < b3 && b3 < c && c < nA)) {
-      st->overflow |= 2;
-      valid = false;
-    }
-    if (!valid) a3 = b3 = c = 0;
-    const uint32_t vmask = valid ? ~0u : 0u;
-    uint32_t y3[W];
-    uint32_t z3[kMaxWN32];
-#pragma unroll
-    for (int k = 0; k < W; ++k)
-      y3[k] = TA[(size_t)a3 * W + k] & TA[(size_t)b3 * W + k] & TA[(size_t)c * W + k] & vmask;
-    uint32_t znz = 0;
-#pragma unroll
-    for (int k = 0; k < kMaxWN32; ++k) {
-      z3[k] = nrm_join(nrm_join(NA[(size_t)a3 * kMaxWN32 + k], NA[(size_t)b3 * kMaxWN32 + k],
-                                P.tn_literal),
-                       NA[(size_t)c * kMaxWN32 + k], P.tn_literal) & vmask;
-      znz |= z3[k];
-    }
-    // visited at depth 4 below the prefix: sorted indices in (idx(c), G-1]
-    if (valid) tl.vis4 += (unsigned long long)(P.G - 1 - w.act[c]);
-    int cmin = valid ? c : 0x7fffffff;
-    for (int o = 32; o > 0; o >>= 1) cmin = min(cmin, __shfl_xor(cmin, o, 64));
-    expand4<W>(P, w, st, y3, z3, znz, valid, a3, b3, c, uniform(cmin), best, tl, inc);
+    tile_item<W64>(P, w, st, it, n, nA, best, tl, inc, lane);
   }
 
   Slot sl = empty_slot();
@@ -262,6 +298,78 @@ __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_df
   v[kTXfp] = tl.xfp;
   block_tally_to(w.tallies + ((size_t)1 * kPersistBlocks + blockIdx.x) * kTallyN, v);
   clear_absent_blocks(w, 1, true);
+}
+
+// The depth-4 tile step of a batched launch: one persistent grid drains the
+// shared queue of every live instance's tiles, one tile per queue position
+// (see k_dfs_multi for the per-instance hand-over).
+template <int W64>
+__global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_dfs4_tiles_multi(
+    const BatchDesc* __restrict__ bd, BatchQueue* __restrict__ bq) {
+  const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
+  const uint32_t total = (uint32_t)uniform((int)bq->total);
+  int cur = -1;
+  uint32_t lo = 0, hi = 0;
+  Problem P;
+  Work w;
+  RoundState* st = nullptr;
+  unsigned long long n = 0;
+  int nA = 0;
+  Best best;
+  Tally tl;
+  unsigned long long inc = 0;
+  auto flush = [&]() {
+    Slot sl = empty_slot();
+    if (best.s >= 0) {
+      sl.s = best.s; sl.tp = best.tp; sl.fp = best.fp;
+      sl.idx[0] = best.idx(0); sl.idx[1] = best.idx(1); sl.idx[2] = best.idx(2);
+      sl.idx[3] = best.idx(3);
+    }
+    unsigned long long v[kTallyN] = {0};
+    if (lane == 0) {
+      v[kTNe4] = tl.ne4;
+      v[kTLeaves] = tl.ne4;
+    }
+    v[kTVis4] = tl.vis4;
+    v[kTXv4] = tl.xv4;
+    v[kTXfp] = tl.xfp;
+    wave_flush(w, st, 1, sl, v);
+  };
+  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
+  const uint32_t gw = blockIdx.x * (kBlock / kWave) + wib;
+  bool first = true;
+  for (;;) {
+    uint32_t g = total;
+    if (first) {
+      g = gw;
+      first = false;
+    } else if (lane == 0) {
+      const unsigned long long c =
+          __hip_atomic_load(&bq->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c + nwaves < total) g = (uint32_t)(nwaves + atomicAdd(&bq->cursor, 1ull));
+    }
+    g = (uint32_t)uniform((int)g);
+    if (g >= total) break;
+    if (g >= hi) {
+      if (cur >= 0) flush();
+      int i = cur + 1;
+      while ((uint32_t)uniform((int)bq->base[i + 1]) <= g) ++i;
+      cur = i;
+      lo = (uint32_t)uniform((int)bq->base[i]);
+      hi = (uint32_t)uniform((int)bq->base[i + 1]);
+      P = bd[i].P;
+      w = bd[i].w;
+      st = w.st;
+      n = st->n_tri < w.tri_cap ? st->n_tri : w.tri_cap;
+      nA = uniform(st->nA);
+      best.init();
+      tl.init();
+      inc = 0;
+    }
+    tile_item<W64>(P, w, st, g - lo, n, nA, best, tl, inc, lane);
+  }
+  if (cur >= 0) flush();
 }
 
 // Blocks of a persistent kernel resident per compute unit, queried once.
@@ -294,7 +402,44 @@ hipError_t launch_tiles_w(const Problem& P, const Work& w, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int W64>
+hipError_t launch_tiles_multi_w(const BatchDesc* bd, BatchQueue* bq, int n_cu, hipStream_t s) {
+  static const int per_cu = resident(&k_dfs4_tiles_multi<W64>);
+  int g = per_cu * (n_cu > 0 ? n_cu : 1);
+  if (g > kPersistBlocks) g = kPersistBlocks;
+  k_dfs4_tiles_multi<W64><<<g, kBlock, 0, s>>>(bd, bq);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_tri_begin_m(const BatchDesc* bd, int n, hipStream_t s) {
+  k_tri_begin_m<<<dim3(64, n), kBlock, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_triples_m(const BatchDesc* bd, int n, hipStream_t s) {
+  k_scan_c_m<<<dim3(1, n), 1024, 0, s>>>(bd);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scatter_c_m<<<dim3(kPersistBlocks / 4, n), kBlock, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_dfs4_tiles_m(int w64, const BatchDesc* bd, BatchQueue* bq, int n_cu,
+                               hipStream_t s) {
+  switch (w64) {
+#define PDFS_CASE(n) \
+  case n:            \
+    return launch_tiles_multi_w<n>(bd, bq, n_cu, s);
+    PDFS_CASE(1) PDFS_CASE(2) PDFS_CASE(3) PDFS_CASE(4) PDFS_CASE(5) PDFS_CASE(6)
+    PDFS_CASE(7) PDFS_CASE(8) PDFS_CASE(10) PDFS_CASE(12) PDFS_CASE(14) PDFS_CASE(16)
+    PDFS_CASE(18) PDFS_CASE(20)
+#undef PDFS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_tri_begin(const Work& w, hipStream_t s) {
   k_tri_begin<<<64, kBlock, 0, s>>>(w);

@@ -153,10 +153,11 @@ Work make_work(pdfs_ctx* c, int w64, int target) {
   w.st = c->st; w.recs = c->recs; w.rec_cap = c->rec_cap;
   w.pair_cap = c->pair_cap; w.item_cap = c->item_cap;
   w.w64 = w64; w.wn32 = 2 * c->wn; w.target = target;
-  w.chunk = c->chunk_items; w.seed_n = c->seed_pairs_n;
+  w.chunk = c->chunk_items; w.seed_n = c->seed_pairs_n; w.long_stream = c->long_stream;
   w.tri = c->tri; w.tri_s = c->tri_s; w.c_hist = c->c_hist;
   w.tri_cap = c->two_phase ? c->tri_cap : 0;
   w.deepq = c->deepq;
+  w.slot_log = nullptr;
   return w;
 }
 
@@ -268,7 +269,8 @@ static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int 
   const Run& r = c->run;
   if (c->use_graphs && !c->time_kernels) {
     const auto key = std::make_tuple(P.h, w.w64, r.p, r.q, r.target, c->prune_mode,
-                                     c->chunk_items, c->seed_pairs_n, c->two_phase);
+                                     c->chunk_items, c->seed_pairs_n, c->two_phase,
+                                     c->long_stream);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
       hipGraph_t g = nullptr;
@@ -305,7 +307,7 @@ static int32_t enqueue_rounds(pdfs_ctx* c, const Problem& P, const Work& w, int 
 // run uses the single-kernel DFS alone.
 static int32_t size_triples(pdfs_ctx* c, int h, int n_unc) {
   c->two_phase = false;
-  if (h != 4 || c->prune_mode != PDFS_PRUNE_EMPTY) return PDFS_OK;
+  if (h != 4 || c->prune_mode != PDFS_PRUNE_EMPTY || !c->split3) return PDFS_OK;
   const int w64 = dfs_row_words(words(n_unc > 0 ? n_unc : 1));
   if (w64 < 0 || w64 > c->w64_max) return PDFS_OK;   // reported when the run starts
   if (!c->c_hist) CK(c, dalloc(c, &c->c_hist, (size_t)c->nA_max + 1));
@@ -347,11 +349,34 @@ static int32_t size_triples(pdfs_ctx* c, int h, int n_unc) {
   return PDFS_OK;
 }
 
+int32_t grow_row_width(pdfs_ctx* c, int w64) {
+  if (w64 <= c->w64_max) return PDFS_OK;
+  // the row-indexed buffers are re-made at the wider stride; the deep walk's
+  // rings (sized by the width) and the captured rounds holding the old
+  // addresses are dropped and re-made on demand
+  void** bufs[] = {(void**)&c->TA, (void**)&c->A8, (void**)&c->deepq};
+  for (void** p : bufs) {
+    dfree(c, *p);
+    *p = nullptr;
+  }
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->w64_max = w64;
+  const size_t rows = (size_t)((c->nA_max + 127) / 128 * 128 + 128);
+  CK(c, dalloc(c, &c->TA, rows * 2 * (size_t)c->w64_max));
+  CK(c, dalloc(c, &c->A8, rows * (size_t)unpacked_row_bytes(c->w64_max)));
+  return PDFS_OK;
+}
+
+int32_t prepare_run(pdfs_ctx* c, int h, int n_unc) {
+  const int32_t rc = ensure_workspace(c, h);
+  if (rc != PDFS_OK) return rc;
+  return size_triples(c, h, n_unc);
+}
+
 int32_t run_start(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int max_rounds,
                   int n_unc) {
-  int32_t rc = ensure_workspace(c, h);
-  if (rc != PDFS_OK) return rc;
-  rc = size_triples(c, h, n_unc);
+  int32_t rc = prepare_run(c, h, n_unc);
   if (rc != PDFS_OK) return rc;
   Run& r = c->run;
   // chunks of an earlier run still in flight are no-ops queued before

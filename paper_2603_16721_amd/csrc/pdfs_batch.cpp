@@ -10,9 +10,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <sys/stat.h>
+#include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -55,19 +59,97 @@ void add_stats(pdfs_stats* dst, const pdfs_stats& s) {
 }
 
 // ------------------------------------------------------------------ tuner
-// The split granularity of the depth-first search -- depth-3 candidates per
-// work item, and in bound mode the number of highest-count pairs expanded
-// before the rest -- changes only scheduling, never results.  The tuner times
-// the first round of a representative instance for each candidate setting
-// and keeps the fastest per instance class (h, row width, active-gene
-// bucket, pruning mode) for the life of the process.
+// How the depth-first search is cut into work changes only scheduling,
+// never results.  The tuner times the first round of a representative
+// instance for each candidate and keeps the fastest per instance class (h,
+// row width, active-gene bucket, pruning mode, device):
+//   * split depth: for h = 4 under empty-prefix pruning, depth-3 prefixes
+//     with long depth-4 streams become work units of their own (listed,
+//     bucketed and expanded in 64-prefix tiles; split depth 3) or stay in
+//     their pair's work item (split depth 2), and the stream length from
+//     which a prefix is listed;
+//   * tile shape of a work item: 64 pairs x `chunk` depth-3 candidates;
+//   * bound mode: the number of highest-count pairs expanded first.
+// Choices are kept for the process and in a JSON file (PDFS_TUNE_CACHE, else
+// $XDG_CACHE_HOME/pdfs/tune.json or ~/.cache/pdfs/tune.json) read when the
+// first batch is tuned and rewritten after every new entry.
+struct TuneChoice {
+  int chunk = 256, seed = 256, split = 3, long_stream = kLongStream;
+  double ms = 0.0;
+};
+using TuneKey = std::tuple<int, int, int, int, std::string>;
+
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tuned;
+std::map<TuneKey, TuneChoice> g_tuned;
+bool g_tune_loaded = false;
 
 int bucket_of(int n) {
   int b = 0;
   while ((1 << (b + 1)) <= n) ++b;
   return b;
+}
+
+std::string tune_cache_path() {
+  if (const char* p = std::getenv("PDFS_TUNE_CACHE")) return p;
+  if (const char* x = std::getenv("XDG_CACHE_HOME")) return std::string(x) + "/pdfs/tune.json";
+  if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/pdfs/tune.json";
+  return std::string();
+}
+
+std::string device_tag(int device) {
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  return std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+}
+
+// One entry per line: {"h":4,"w":16,"g":13,"mode":1,"device":"gfx950...","chunk":256,
+// "seed":256,"split":3,"long_stream":384,"ms":1.23}
+void load_tune_cache() {
+  g_tune_loaded = true;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    int h = 0, w = 0, g = 0, mode = 0;
+    TuneChoice c;
+    char dev[128] = {0};
+    if (std::sscanf(line,
+                    " {\"h\":%d,\"w\":%d,\"g\":%d,\"mode\":%d,\"device\":\"%127[^\"]\","
+                    "\"chunk\":%d,\"seed\":%d,\"split\":%d,\"long_stream\":%d,\"ms\":%lf",
+                    &h, &w, &g, &mode, dev, &c.chunk, &c.seed, &c.split, &c.long_stream,
+                    &c.ms) == 10)
+      g_tuned[std::make_tuple(h, w, g, mode, std::string(dev))] = c;
+  }
+  std::fclose(f);
+}
+
+void save_tune_cache() {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  // the directory chain, one level at a time (existing levels are kept)
+  const size_t slash = path.rfind('/');
+  for (size_t i = path.find('/', 1); slash != std::string::npos && i != std::string::npos && i <= slash;
+       i = path.find('/', i + 1))
+    (void)mkdir(path.substr(0, i).c_str(), 0755);
+  const std::string tmp = path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "[\n");
+  size_t k = 0;
+  for (const auto& kv : g_tuned) {
+    const TuneChoice& c = kv.second;
+    std::fprintf(f,
+                 "{\"h\":%d,\"w\":%d,\"g\":%d,\"mode\":%d,\"device\":\"%s\",\"chunk\":%d,"
+                 "\"seed\":%d,\"split\":%d,\"long_stream\":%d,\"ms\":%.4f}%s\n",
+                 std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                 std::get<3>(kv.first), std::get<4>(kv.first).c_str(), c.chunk, c.seed, c.split,
+                 c.long_stream, c.ms, ++k < g_tuned.size() ? "," : "");
+  }
+  std::fprintf(f, "]\n");
+  std::fclose(f);
+  (void)std::rename(tmp.c_str(), path.c_str());
 }
 
 double time_first_round(pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
@@ -78,40 +160,69 @@ double time_first_round(pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
   return std::chrono::duration<double>(Clock::now() - t0).count();
 }
 
+void apply(pdfs_ctx* c, const TuneChoice& t) {
+  c->chunk_items = t.chunk;
+  c->seed_pairs_n = t.seed;
+  c->split3 = t.split == 3;
+  c->long_stream = t.long_stream;
+}
+
 void autotune(pdfs_ctx* c, int h, uint32_t p, uint32_t q) {
   if (h < 3) return;
-  const auto key = std::make_tuple(h, dfs_row_words((c->n_tumor + 63) / 64), bucket_of(c->nA_max),
-                                   c->prune_mode);
+  const TuneKey key = std::make_tuple(h, dfs_row_words((c->n_tumor + 63) / 64),
+                                      bucket_of(c->nA_max), c->prune_mode, device_tag(c->device));
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
+    if (!g_tune_loaded) load_tune_cache();
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-      c->chunk_items = it->second.first;
-      c->seed_pairs_n = it->second.second;
+      apply(c, it->second);
       return;
     }
   }
+  std::vector<TuneChoice> cand;
   static const int chunks[] = {64, 128, 256, 512, 1024};
   static const int seeds[] = {128, 256, 1024};
-  const int nseed = c->prune_mode == PDFS_PRUNE_BOUND ? 3 : 1;
-  double best = 1e30;
-  int bc = c->chunk_items, bs = c->seed_pairs_n;
-  c->chunk_items = 256;
-  c->seed_pairs_n = 256;
-  (void)time_first_round(c, h, p, q);   // warm-up (allocations, graph capture)
+  static const int streams[] = {256, 384, 768};
+  const bool bound = c->prune_mode == PDFS_PRUNE_BOUND;
+  const bool split_choice = h == 4 && c->prune_mode == PDFS_PRUNE_EMPTY;
   for (int ci : chunks) {
-    for (int si = 0; si < nseed; ++si) {
-      c->chunk_items = ci;
-      c->seed_pairs_n = nseed == 1 ? 256 : seeds[si];
-      double t = time_first_round(c, h, p, q);
-      t = std::min(t, time_first_round(c, h, p, q));
-      if (t < best) { best = t; bc = c->chunk_items; bs = c->seed_pairs_n; }
+    TuneChoice t;
+    t.chunk = ci;
+    if (bound) {
+      for (int sd : seeds) {
+        t.seed = sd;
+        cand.push_back(t);
+      }
+    } else if (split_choice) {
+      t.split = 2;
+      cand.push_back(t);
+      t.split = 3;
+      for (int ls : streams) {
+        t.long_stream = ls;
+        cand.push_back(t);
+      }
+    } else {
+      cand.push_back(t);
     }
   }
-  c->chunk_items = bc;
-  c->seed_pairs_n = bs;
+  TuneChoice best;
+  best.ms = 1e30;
+  apply(c, TuneChoice());
+  (void)time_first_round(c, h, p, q);   // warm-up (allocations, graph capture)
+  for (const TuneChoice& t : cand) {
+    apply(c, t);
+    double s = time_first_round(c, h, p, q);
+    s = std::min(s, time_first_round(c, h, p, q));
+    if (s * 1e3 < best.ms) {
+      best = t;
+      best.ms = s * 1e3;
+    }
+  }
+  apply(c, best);
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tuned[key] = {bc, bs};
+  g_tuned[key] = best;
+  save_tune_cache();
 }
 
 }  // namespace
@@ -123,6 +234,23 @@ struct pdfs_batch {
   std::vector<hipStream_t> streams;
   std::vector<pdfs_ctx*> ctx;
   std::string err;
+  // ---- one launch per round step over every instance (h in {3, 4})
+  hipStream_t ms = nullptr;                  // stream of the batched launches
+  RoundState* st_all = nullptr;              // device: round state of each instance
+  RoundState* h_st_all = nullptr;            // pinned: kDepth copies of st_all
+  Slot* logs = nullptr;                      // device: per instance, phase: kLogCap leaves
+  BatchQueue* queues = nullptr;              // device: one per h group and kind
+  // per grouping of the instances into row-width ranges: the descriptor
+  // array (every instance at its range's width) and the captured round
+  std::map<std::vector<int>, BatchDesc*> descs;
+  std::map<std::vector<int>, bool> desc_fresh;   // uploaded for the current run
+  std::map<std::pair<std::vector<int>, int>, hipGraphExec_t> graphs;
+  int max_ranges = 0;                        // ranges per h (0: 1 bound, 4 empty)
+  hipEvent_t done_ev[kDepth] = {};
+  hipEvent_t fork_ev = nullptr;              // ranges' depth-first launches run side by side
+  std::vector<hipEvent_t> join_ev;
+  int n_alloc = 0;                           // instances the batched buffers hold
+  bool streams_only = false;                 // PDFS_OPT_BATCH_STREAMS: no batched launches
 };
 
 namespace {
@@ -141,6 +269,410 @@ int32_t batch_fail(pdfs_batch* b, int32_t code, int inst) {
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Batched runs as one launch per round step.  Instances are ordered h = 3
+// first, then h = 4 (the depth-first kernels are built per h); every light
+// step covers all of them with one block row per instance, each depth-first
+// step drains one shared queue per h group.  The row width of a chunk of
+// rounds is the largest any live instance needs (narrower instances run at
+// it: any width >= ceil(|U|/64) gives the same results).
+constexpr int kMaxRanges = 8;   // row-width ranges per h
+
+struct MultiRun {
+  int n = 0;
+  std::vector<int> order;    // position -> instance index (h = 3 first, widest first)
+  int max_G = 0;
+  int n_cu = 256;
+  bool bound = false;
+  bool tiles = false;        // some instance uses the two-phase depth 4
+  int max_ranges = 1;        // row-width ranges per h
+  uint32_t p = 1, q = 1;
+  std::vector<int> target;   // per position
+  std::vector<int> h;        // per position
+};
+
+// A grouping: consecutive ranges of positions with one row width each,
+// flattened as (h, first position, count, w64) quadruples.
+using Grouping = std::vector<int>;
+
+// Ranges of equal h over the fixed position order, each at the widest width
+// its live members need (done instances need nothing); adjacent ranges merge
+// (the wider width wins) until each h has at most max_ranges, the pair whose
+// widths are closest first.
+Grouping make_grouping(const MultiRun& m, const std::vector<int>& need) {
+  Grouping g;
+  for (int hh = 3; hh <= 4; ++hh) {
+    std::vector<std::array<int, 3>> r;   // first, count, width
+    for (int k = 0; k < m.n; ++k) {
+      if (m.h[k] != hh) continue;
+      const int wk = need[k];
+      if (!r.empty() && (r.back()[2] == wk || wk == 0)) {
+        r.back()[1] += 1;
+      } else if (!r.empty() && r.back()[2] == 0) {
+        r.back()[1] += 1;
+        r.back()[2] = wk;
+      } else {
+        r.push_back({k, 1, wk});
+      }
+    }
+    while ((int)r.size() > m.max_ranges) {
+      size_t best = 0;
+      double ratio = 1e30;
+      for (size_t j = 0; j + 1 < r.size(); ++j) {
+        const double a = std::max(1, r[j][2]), c = std::max(1, r[j + 1][2]);
+        const double x = std::max(a, c) / std::min(a, c);
+        if (x < ratio) { ratio = x; best = j; }
+      }
+      r[best][1] += r[best + 1][1];
+      r[best][2] = std::max(r[best][2], r[best + 1][2]);
+      r.erase(r.begin() + (long)best + 1);
+    }
+    for (const auto& x : r) {
+      g.push_back(hh);
+      g.push_back(x[0]);
+      g.push_back(x[1]);
+      g.push_back(std::max(1, x[2]));
+    }
+  }
+  return g;
+}
+
+#define BCK(expr)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return batch_fail(b, e_ == hipErrorOutOfMemory ? PDFS_ERR_OUT_OF_MEMORY : PDFS_ERR_DEVICE, \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+int32_t ensure_multi_buffers(pdfs_batch* b, int n) {
+  if (b->n_alloc >= n) return PDFS_OK;
+  if (b->st_all) (void)hipFree(b->st_all);
+  if (b->h_st_all) (void)hipHostFree(b->h_st_all);
+  if (b->logs) (void)hipFree(b->logs);
+  b->st_all = nullptr;
+  b->h_st_all = nullptr;
+  b->logs = nullptr;
+  BCK(hipMalloc(reinterpret_cast<void**>(&b->st_all), sizeof(RoundState) * n));
+  BCK(hipHostMalloc(reinterpret_cast<void**>(&b->h_st_all), sizeof(RoundState) * n * kDepth,
+                    hipHostMallocDefault));
+  BCK(hipMalloc(reinterpret_cast<void**>(&b->logs),
+                sizeof(Slot) * (size_t)n * kSlotPhases * kLogCap));
+  if (!b->queues)
+    BCK(hipMalloc(reinterpret_cast<void**>(&b->queues), sizeof(BatchQueue) * 2 * kMaxRanges * 2));
+  for (hipEvent_t& e : b->done_ev)
+    if (!e) BCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (!b->fork_ev) BCK(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  while ((int)b->join_ev.size() < 2 * kMaxRanges) {
+    hipEvent_t e = nullptr;
+    BCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b->join_ev.push_back(e);
+  }
+  // descriptor arrays and graphs hold the old addresses
+  for (auto& kv : b->descs) (void)hipFree(kv.second);
+  b->descs.clear();
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+  b->n_alloc = n;
+  return PDFS_OK;
+}
+
+// The descriptor array of a grouping for this run (uploaded on first use;
+// never rewritten while the run may still read it).
+int32_t descs_for(pdfs_batch* b, const MultiRun& m, const Grouping& g, BatchDesc** out) {
+  auto it = b->descs.find(g);
+  if (it == b->descs.end()) {
+    BatchDesc* d = nullptr;
+    BCK(hipMalloc(reinterpret_cast<void**>(&d), sizeof(BatchDesc) * m.n));
+    it = b->descs.emplace(g, d).first;
+    b->desc_fresh[g] = false;
+  }
+  if (!b->desc_fresh[g]) {
+    std::vector<BatchDesc> h((size_t)m.n);
+    for (size_t r = 0; r < g.size(); r += 4) {
+      const int w64 = g[r + 3];
+      for (int k = g[r + 1]; k < g[r + 1] + g[r + 2]; ++k) {
+        pdfs_ctx* c = b->ctx[m.order[k]];
+        // the instance's row buffers must hold rows of this width
+        if (w64 > c->w64_max)
+          return batch_fail(b, PDFS_ERR_DEVICE, "instance " + std::to_string(m.order[k]) +
+                                                    ": row buffers narrower than its range");
+        h[k].P = make_problem(c, m.h[k], m.p, m.q);
+        Work w = make_work(c, w64, m.target[k]);
+        w.st = b->st_all + k;
+        w.slot_log = b->logs + (size_t)k * kSlotPhases * kLogCap;
+        h[k].w = w;
+      }
+    }
+    BCK(hipMemcpy(it->second, h.data(), sizeof(BatchDesc) * m.n, hipMemcpyHostToDevice));
+    b->desc_fresh[g] = true;
+  }
+  *out = it->second;
+  return PDFS_OK;
+}
+
+// One round of every instance: light steps over all, depth-first steps per
+// range (one shared queue and one launch at the range's width each).
+int32_t enqueue_multi_round(pdfs_batch* b, const MultiRun& m, BatchDesc* bd, const Grouping& g) {
+  hipStream_t s = b->ms;
+  const int n = m.n;
+  BCK(launch_round_begin_m(bd, n, s));
+  BCK(launch_active_m(bd, n, m.max_G, s));
+  BCK(launch_gather_active_m(bd, n, m.max_G, s));
+  BCK(launch_pairs_m(bd, n, s));
+  // The ranges of a depth-first step go out side by side on the batch's
+  // streams (fork from and join back into the round's stream), so that one
+  // range's tail overlaps the next range's work.
+  const int nr = (int)g.size() / 4;
+  auto range_stream = [&](int r) { return b->streams[(size_t)r % b->streams.size()]; };
+  auto fork = [&]() -> int32_t {
+    if (nr < 2) return PDFS_OK;
+    BCK(hipEventRecord(b->fork_ev, s));
+    for (int r = 1; r < nr && r < (int)b->streams.size(); ++r)
+      BCK(hipStreamWaitEvent(range_stream(r), b->fork_ev, 0));
+    return PDFS_OK;
+  };
+  auto join = [&]() -> int32_t {
+    if (nr < 2) return PDFS_OK;
+    for (int r = 1; r < nr && r < (int)b->streams.size(); ++r) {
+      BCK(hipEventRecord(b->join_ev[r], range_stream(r)));
+      BCK(hipStreamWaitEvent(s, b->join_ev[r], 0));
+    }
+    return PDFS_OK;
+  };
+  auto dfs_step = [&](int phase) -> int32_t {
+    int32_t e = fork();
+    if (e != PDFS_OK) return e;
+    for (int r = 0; r < nr; ++r) {
+      const int* x = &g[(size_t)r * 4];
+      BatchQueue* q = b->queues + r;
+      BCK(launch_batch_queue(bd + x[1], x[2], q, phase, 0, range_stream(r)));
+      BCK(launch_dfs_m(x[0], x[3], m.bound, bd + x[1], q, phase, m.n_cu, range_stream(r)));
+    }
+    return join();
+  };
+  int32_t rc = PDFS_OK;
+  if (m.bound) {
+    BCK(launch_seed_select_m(bd, n, s));
+    BCK(launch_make_items_m(bd, n, true, s));
+    if ((rc = dfs_step(1)) != PDFS_OK) return rc;
+    BCK(launch_filter_pairs_m(bd, n, s));
+    BCK(launch_make_items_m(bd, n, false, s));
+    if ((rc = dfs_step(2)) != PDFS_OK) return rc;
+  } else {
+    BCK(launch_use_all_pairs_m(bd, n, s));
+    BCK(launch_make_items_m(bd, n, false, s));
+    if (m.tiles) BCK(launch_tri_begin_m(bd, n, s));
+    if ((rc = dfs_step(2)) != PDFS_OK) return rc;
+    if (m.tiles) {
+      BCK(launch_sort_triples_m(bd, n, s));
+      if ((rc = fork()) != PDFS_OK) return rc;
+      for (int r = 0; r < nr; ++r) {
+        const int* x = &g[(size_t)r * 4];
+        if (x[0] != 4) continue;
+        BatchQueue* q = b->queues + 2 * kMaxRanges + r;
+        BCK(launch_batch_queue(bd + x[1], x[2], q, 1, 1, range_stream(r)));
+        BCK(launch_dfs4_tiles_m(x[3], bd + x[1], q, m.n_cu, range_stream(r)));
+      }
+      if ((rc = join()) != PDFS_OK) return rc;
+    }
+  }
+  BCK(launch_finish_round_m(bd, n, s));
+  return PDFS_OK;
+}
+
+// `rounds` batched rounds of a grouping: replays of one captured round.
+int32_t enqueue_multi_rounds(pdfs_batch* b, const MultiRun& m, const Grouping& g, int rounds) {
+  BatchDesc* bd = nullptr;
+  int32_t rc = descs_for(b, m, g, &bd);
+  if (rc != PDFS_OK) return rc;
+  const auto key = std::make_pair(g, (m.bound ? 1 : 0) | (m.tiles ? 2 : 0));
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    BCK(hipStreamBeginCapture(b->ms, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_multi_round(b, m, bd, g);
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->ms, &gr);
+    if (rc != PDFS_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    BCK(ec);
+    hipGraphExec_t e = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&e, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    BCK(ei);
+    it = b->graphs.emplace(key, e).first;
+  }
+  for (int k = 0; k < rounds; ++k) BCK(hipGraphLaunch(it->second, b->ms));
+  return PDFS_OK;
+}
+
+int words64(int n) { return (n + 63) / 64; }
+
+// The greedy loop of every instance through batched launches.
+int32_t run_multi(pdfs_batch* b, const int32_t* h, uint32_t p, uint32_t q, const int32_t* target,
+                  pdfs_combo* const* outs, const int32_t* caps, int32_t* n_outs, pdfs_stats* stats,
+                  std::chrono::steady_clock::time_point t0) {
+  const int n = (int)b->ctx.size();
+  MultiRun m;
+  m.n = n;
+  m.p = p;
+  m.q = q;
+  m.bound = b->ctx[0]->prune_mode == PDFS_PRUNE_BOUND;
+  m.n_cu = b->ctx[0]->n_cu;
+  m.max_ranges = b->max_ranges > 0 ? std::min(b->max_ranges, kMaxRanges) : (m.bound ? 1 : 4);
+  int32_t rc = ensure_multi_buffers(b, n);
+  if (rc != PDFS_OK) return rc;
+  // earlier work of the instances (creation, tuning) may sit on any of the
+  // batch's streams; everything below runs on one
+  for (hipStream_t s : b->streams) BCK(hipStreamSynchronize(s));
+  b->ms = b->streams[0];
+  for (auto& kv : b->desc_fresh) kv.second = false;
+  std::vector<int> w0((size_t)n);   // first-round width of each instance
+  for (int i = 0; i < n; ++i) {
+    pdfs_ctx* c = b->ctx[i];
+    c->stream = b->ms;
+    const int32_t u = set_uncovered(c, nullptr);
+    if (u < 0) return batch_fail(b, u, i);
+    rc = prepare_run(c, h[i], u);
+    if (rc != PDFS_OK) return batch_fail(b, rc, i);
+    m.tiles = m.tiles || c->two_phase;
+    // counter rows: the batched kernels write row 0 of a phase (and the pair
+    // table its first rows); the rest must read zero
+    BCK(launch_zero_u32(c->tallies, (size_t)kSlotPhases * kPersistBlocks * kTallyN * 2, b->ms));
+    w0[i] = dfs_row_words(words64(u > 0 ? u : 1));
+    if (w0[i] < 0) return batch_fail(b, PDFS_ERR_UNSUPPORTED, "row too wide");
+    m.max_G = std::max(m.max_G, c->G);
+  }
+  // positions: h = 3 first, then h = 4, each widest first, so that instances
+  // of close widths sit in one range
+  for (int hh = 3; hh <= 4; ++hh) {
+    std::vector<int> idx;
+    for (int i = 0; i < n; ++i)
+      if (h[i] == hh) idx.push_back(i);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return w0[a] > w0[c]; });
+    m.order.insert(m.order.end(), idx.begin(), idx.end());
+  }
+  std::vector<int> need((size_t)n);
+  for (int k = 0; k < n; ++k) {
+    const int i = m.order[k];
+    m.h.push_back(h[i]);
+    m.target.push_back(target && target[i] > 0 ? target[i] : b->ctx[i]->n_tumor);
+    need[k] = w0[i];
+  }
+  Grouping g = make_grouping(m, need);
+  // an instance's rows are packed at its range's width; ranges merge and
+  // split as the run goes on, but no width exceeds the widest first-round
+  // one, to which every instance's row buffers are regrown
+  const int w_all = *std::max_element(w0.begin(), w0.end());
+  for (int i = 0; i < n; ++i) {
+    rc = grow_row_width(b->ctx[i], w_all);
+    if (rc != PDFS_OK) return batch_fail(b, rc, i);
+  }
+  {
+    BatchDesc* bd = nullptr;
+    if ((rc = descs_for(b, m, g, &bd)) != PDFS_OK) return rc;
+    BCK(launch_run_begin_m(bd, n, 0, b->ms));
+  }
+  // chunks of batched rounds, kDepth in flight, each ending with a copy of
+  // every instance's state; the grouping of a chunk comes from the newest
+  // states read
+  int inflight = 0, slot = 0, chunk = 1;
+  int executed_before = 0;
+  auto t_prev = Clock::now();
+  const RoundState* hs = nullptr;
+  bool finished = false;
+  while (!finished) {
+    while (inflight < kDepth) {
+      const int sl = (slot + inflight) % kDepth;
+      if ((rc = enqueue_multi_rounds(b, m, g, chunk)) != PDFS_OK) return rc;
+      BCK(hipMemcpyAsync(b->h_st_all + (size_t)sl * n, b->st_all, sizeof(RoundState) * n,
+                         hipMemcpyDeviceToHost, b->ms));
+      BCK(hipEventRecord(b->done_ev[sl], b->ms));
+      ++inflight;
+    }
+    BCK(hipEventSynchronize(b->done_ev[slot]));
+    hs = b->h_st_all + (size_t)slot * n;
+    --inflight;
+    slot = (slot + 1) % kDepth;
+    finished = true;
+    int executed = 0;
+    for (int k = 0; k < n; ++k) {
+      const RoundState& st = hs[k];
+      if (st.overflow & 2) return batch_fail(b, PDFS_ERR_DEVICE, "instance " +
+                                             std::to_string(m.order[k]) + ": corrupt result slot");
+      if (st.overflow)
+        return batch_fail(b, PDFS_ERR_OUT_OF_MEMORY, "instance " + std::to_string(m.order[k]) +
+                                                     ": list capacity exceeded");
+      if (st.executed > b->ctx[m.order[k]]->n_tumor + 2)
+        return batch_fail(b, PDFS_ERR_DEVICE, "greedy loop did not stop");
+      executed = std::max(executed, st.executed);
+      if (st.done) {
+        need[k] = 0;
+        continue;
+      }
+      finished = false;
+      const int unc = b->ctx[m.order[k]]->n_tumor - st.covered;
+      need[k] = std::min(need[k], dfs_row_words(words64(unc > 0 ? unc : 1)));
+    }
+    g = make_grouping(m, need);
+    const auto now = Clock::now();
+    const double ns = (double)std::chrono::duration_cast<std::chrono::nanoseconds>(now - t_prev).count();
+    t_prev = now;
+    const int ran = executed - executed_before;
+    executed_before = executed;
+    if (ran > 0) {
+      int c = (int)(1.0e6 / (ns / ran));
+      c = c < 1 ? 1 : (c > kMaxChunk ? kMaxChunk : c);
+      chunk = c > 2 * chunk ? 2 * chunk : c;
+    }
+  }
+  // the chunks still in flight are no-ops; wait for them before reading
+  BCK(hipStreamSynchronize(b->ms));
+  int32_t result = PDFS_OK;
+  for (int k = 0; k < n; ++k) {
+    const int i = m.order[k];
+    pdfs_ctx* c = b->ctx[i];
+    const RoundState& st = hs[k];
+    const int rounds = st.rounds;
+    n_outs[i] = rounds;
+    const int cap = caps ? caps[i] : 0;
+    const int nc = std::min(rounds, cap);
+    if (nc > 0 && outs && outs[i]) {
+      std::vector<RoundRecord> recs((size_t)nc);
+      BCK(hipMemcpy(recs.data(), c->recs, sizeof(RoundRecord) * nc, hipMemcpyDeviceToHost));
+      for (int r = 0; r < nc; ++r) fill_combo(&outs[i][r], recs[r], h[i]);
+    }
+    if (rounds > cap) {
+      result = PDFS_ERR_TRUNCATED;
+      b->err = "instance " + std::to_string(i) + ": more rounds than its cap";
+    }
+    if (stats) {
+      for (int l = 0; l <= PDFS_MAX_H; ++l) {
+        stats->visited[l] += st.tot.visited[l];
+        stats->nonempty[l] += st.tot.nonempty[l];
+        stats->bound_pruned[l] += st.tot.bound_pruned[l];
+      }
+      stats->rounds += st.rounds;
+      stats->pair_macs += st.tx_pair_macs;
+      stats->dfs_visits[3] += st.tx_vis3;
+      stats->dfs_visits[4] += st.tx_vis4;
+      stats->dfs_leaves += st.tx_leaves;
+      stats->dfs_fp_leaves += st.tx_fp_leaves;
+      stats->dfs_visit_words3 += st.tx_vis_words3;
+      stats->dfs_visit_words4 += st.tx_vis_words4;
+    }
+  }
+  if (stats)
+    stats->ns_total = std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count();
+  return result;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pdfs_batch_last_error(const pdfs_batch* b) {
@@ -155,6 +687,7 @@ int32_t pdfs_batch_create(const pdfs_matrix* inst, int32_t n, const pdfs_options
   pdfs_batch* b = new pdfs_batch();
   b->device = opt ? opt->device : 0;
   b->autotune = opt && (opt->flags & PDFS_OPT_AUTOTUNE);
+  b->streams_only = opt && (opt->flags & PDFS_OPT_BATCH_STREAMS);
   if (hipSetDevice(b->device) != hipSuccess) {
     delete b;
     return ctx_fail(nullptr, PDFS_ERR_DEVICE, "hipSetDevice failed");
@@ -201,6 +734,12 @@ int32_t pdfs_batch_run(pdfs_batch* b, const int32_t* h, uint32_t p, uint32_t q,
   }
   if (b->autotune)
     for (int i = 0; i < n; ++i) autotune(b->ctx[i], h[i], p, q);
+  // one launch per round step over every instance when all take it (h = 3, 4
+  // with empty or bound pruning); the stream-parallel runs below otherwise
+  bool multi = n <= kMaxBatch && b->ctx[0]->prune_mode != PDFS_PRUNE_NONE && !b->streams_only;
+  for (int i = 0; i < n; ++i)
+    multi = multi && (h[i] == 3 || h[i] == 4) && b->ctx[i]->tn_literal == b->ctx[0]->tn_literal;
+  if (multi) return run_multi(b, h, p, q, target, outs, caps, n_outs, stats, t0);
   for (int i = 0; i < n; ++i) {
     pdfs_ctx* c = b->ctx[i];
     begin_stats(c, nullptr);
@@ -267,6 +806,17 @@ int32_t pdfs_batch_run(pdfs_batch* b, const int32_t* h, uint32_t p, uint32_t q,
 void pdfs_batch_destroy(pdfs_batch* b) {
   if (!b) return;
   (void)hipSetDevice(b->device);
+  for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : b->descs) (void)hipFree(kv.second);
+  if (b->st_all) (void)hipFree(b->st_all);
+  if (b->h_st_all) (void)hipHostFree(b->h_st_all);
+  if (b->logs) (void)hipFree(b->logs);
+  if (b->queues) (void)hipFree(b->queues);
+  for (hipEvent_t e : b->done_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  for (hipEvent_t e : b->join_ev) (void)hipEventDestroy(e);
   for (pdfs_ctx* c : b->ctx) pdfs_destroy(c);
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   delete b;

@@ -89,6 +89,8 @@ struct RoundState {
   // ---- two-phase depth-4 (h = 4, empty-prefix pruning)
   unsigned long long n_tri;        // non-empty depth-3 prefixes listed this round
   unsigned long long tri_cursor;   // tile cursor of the depth-4 kernel
+  // ---- batched launches: best-leaf log entries per slot phase this round
+  uint32_t nlog[4];
 };
 
 // Per-block counter rows (summed by the round's finish kernel instead of
@@ -172,6 +174,8 @@ struct Work {
   int32_t target;    // covered-count stop target
   int32_t chunk;     // depth-3 candidates per main-phase DFS item
   int32_t seed_n;    // bound mode: pairs expanded in the seed phase
+  int32_t long_stream;   // two-phase depth 4: prefixes with at least this many
+                         // depth-4 candidates are listed for the tile kernel
   // two-phase depth-4: listed triples a | b << 16 | c << 32, the same sorted
   // by c, and per-c counts (then bucket offsets), nA entries
   unsigned long long* tri;
@@ -182,6 +186,32 @@ struct Work {
   // kDeepQ entries ([tumour word][entry] intersections, then [depth][entry]
   // indices) and a frame for a suspended expansion ([word][lane])
   uint32_t* deepq;
+  // batched launches: per slot phase, kLogCap best leaves appended by the
+  // waves that worked on this instance (NULL for a context's own launches,
+  // whose slots are one per block)
+  Slot* slot_log;
+};
+
+// ---------------------------------------------------------------- batched
+// Many cohorts' rounds in one launch per round step.  Light steps run one
+// block row per instance (blockIdx.y); the depth-first steps drain one shared
+// queue of (instance, item) work: instance i owns the queue positions
+// [base[i], base[i+1]).  A wave's best leaf and counts for an instance go to
+// that instance's log and counter row when the wave moves on (a wave's queue
+// positions only grow, so it meets each instance at most once per launch).
+constexpr int kMaxBatch = 64;
+constexpr int kLogCap = kWavesPerGrid;
+
+struct BatchDesc {
+  Problem P;
+  Work w;
+};
+
+struct BatchQueue {
+  unsigned long long cursor;
+  uint32_t n;       // instances
+  uint32_t total;   // queue length (base[n])
+  uint32_t base[kMaxBatch + 1];
 };
 
 // ---------------------------------------------------------------- launchers
@@ -229,5 +259,28 @@ hipError_t launch_clear_slots(Slot* slots, int n, hipStream_t s);
 hipError_t launch_zero_u32(void* p, size_t n32, hipStream_t s);
 hipError_t launch_fill_u(uint64_t* U, int wt, int n, hipStream_t s);
 hipError_t launch_run_begin(const Problem& P, const Work& w, int max_rounds, hipStream_t s);
+
+// batched launches over n instances (descriptors bd in device memory; every
+// instance at the same row width, h in {3, 4}); the depth-first steps take a
+// queue built by launch_batch_queue over the instances they cover (kind 0:
+// work items, 1: depth-4 tiles)
+hipError_t launch_run_begin_m(const BatchDesc* bd, int n, int max_rounds, hipStream_t s);
+hipError_t launch_round_begin_m(const BatchDesc* bd, int n, hipStream_t s);
+hipError_t launch_active_m(const BatchDesc* bd, int n, int max_G, hipStream_t s);
+hipError_t launch_gather_active_m(const BatchDesc* bd, int n, int max_G, hipStream_t s);
+hipError_t launch_pairs_m(const BatchDesc* bd, int n, hipStream_t s);
+hipError_t launch_seed_select_m(const BatchDesc* bd, int n, hipStream_t s);
+hipError_t launch_make_items_m(const BatchDesc* bd, int n, bool seed, hipStream_t s);
+hipError_t launch_filter_pairs_m(const BatchDesc* bd, int n, hipStream_t s);
+hipError_t launch_use_all_pairs_m(const BatchDesc* bd, int n, hipStream_t s);
+hipError_t launch_batch_queue(const BatchDesc* bd, int n, BatchQueue* bq, int phase, int kind,
+                              hipStream_t s);
+hipError_t launch_dfs_m(int h, int w64, bool bound, const BatchDesc* bd, BatchQueue* bq,
+                        int phase, int n_cu, hipStream_t s);
+hipError_t launch_tri_begin_m(const BatchDesc* bd, int n, hipStream_t s);
+hipError_t launch_sort_triples_m(const BatchDesc* bd, int n, hipStream_t s);
+hipError_t launch_dfs4_tiles_m(int w64, const BatchDesc* bd, BatchQueue* bq, int n_cu,
+                               hipStream_t s);
+hipError_t launch_finish_round_m(const BatchDesc* bd, int n, hipStream_t s);
 
 }  // namespace pdfs

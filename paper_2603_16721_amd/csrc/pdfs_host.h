@@ -99,6 +99,9 @@ struct pdfs_ctx {
   int chunk_items = 256;               // depth-3 candidates per DFS work item
   int n_cu = 256;                      // compute units of the device
   int seed_pairs_n = 256;              // bound mode: pairs expanded first
+  int long_stream = pdfs::kLongStream; // two-phase depth 4: listing threshold
+  bool split3 = true;                  // h = 4, empty mode: long-stream prefixes as
+                                       // depth-3 work units (the two-phase path)
   hipEvent_t ev[pdfs::kDepth][pdfs::kMaxChunk][5] = {};
   hipEvent_t chunk_done[pdfs::kDepth] = {};
   int chunk_rounds[pdfs::kDepth] = {};   // rounds of the chunk that uses each slot
@@ -108,8 +111,8 @@ struct pdfs_ctx {
   int32_t kernel_launches[3] = {0, 0, 0};
   pdfs::Run run;
   // captured round graphs keyed by (h, w64, p, q, target, mode, chunk, seed,
-  // two-phase)
-  std::map<std::tuple<int, int, uint32_t, uint32_t, int, int, int, int, bool>, hipGraphExec_t>
+  // two-phase, long-stream threshold)
+  std::map<std::tuple<int, int, uint32_t, uint32_t, int, int, int, int, bool, int>, hipGraphExec_t>
       graphs;
   size_t bytes = 0;                    // device bytes held (admission accounting)
   bool async_alloc = false;            // stream-ordered allocation (batched / served)
@@ -127,6 +130,12 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
 void begin_stats(pdfs_ctx* c, pdfs_stats* st);
 void end_stats(pdfs_ctx* c, pdfs_stats* st, std::chrono::steady_clock::time_point t0);
 const std::string& create_error();
+// Row-indexed buffers (re-packed rows, unpacked bytes) regrown to hold rows of
+// w64 words (batched launches run every instance at the widest width).
+int32_t grow_row_width(pdfs_ctx* c, int w64);
+// Workspace of a run of depth h from |U| = n_unc: lists allocated, and for
+// the two-phase path the prefix lists sized by a counting pass.
+int32_t prepare_run(pdfs_ctx* c, int h, int n_unc);
 // Starts a greedy run (U must already hold the starting mask on c->stream).
 int32_t run_start(pdfs_ctx* c, int h, uint32_t p, uint32_t q, int target, int max_rounds,
                   int n_unc);

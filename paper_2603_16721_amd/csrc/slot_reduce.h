@@ -68,4 +68,28 @@ __device__ __forceinline__ void block_tally_to(unsigned long long* row,
   }
 }
 
+// Batched launches: a wave leaving an instance sends its best leaf (if any) to
+// the instance's log of the phase and adds its counts to the instance's
+// counter row of the phase (row 0; the other rows stay zero).  vals: as for
+// block_tally_to.
+__device__ __forceinline__ void wave_flush(const Work& w, RoundState* st, int phase, Slot b,
+                                           unsigned long long (&vals)[kTallyN]) {
+  b = wave_best(b);
+  for (int f = 0; f < kTallyN; ++f) {
+    unsigned long long v = vals[f];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    vals[f] = v;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (b.s >= 0) {
+      const uint32_t pos = atomicAdd(&st->nlog[phase], 1u);
+      if (pos < (uint32_t)kLogCap) w.slot_log[(size_t)phase * kLogCap + pos] = b;
+      else atomicOr(&st->overflow, 1);
+    }
+    unsigned long long* row = w.tallies + (size_t)phase * kPersistBlocks * kTallyN;
+    for (int f = 0; f < kTallyN; ++f)
+      if (vals[f]) atomicAdd(&row[f], vals[f]);
+  }
+}
+
 }  // namespace pdfs

@@ -77,6 +77,7 @@ PDFS_NOALLOC_SCRATCH_BYTES = 64 << 20
 PDFS_OPT_GRAPHS = 2
 PDFS_OPT_AUTOTUNE = 4
 PDFS_OPT_TN_LITERAL = 8
+PDFS_OPT_BATCH_STREAMS = 16
 
 
 def _load():
@@ -319,8 +320,11 @@ class Solver:
                             n_tumor=self.n_tumor)
 
 
-def pdfs_batch_create(instances, prune_mode="bound", device=0, autotune=False):
-    """instances: list of (tumor, normal, n_tumor, n_normal) host arrays.  Returns a handle."""
+def pdfs_batch_create(instances, prune_mode="bound", device=0, autotune=False,
+                      streams_only=False):
+    """instances: list of (tumor, normal, n_tumor, n_normal) host arrays.  Returns a handle.
+    streams_only: each instance's own launches on the batch's streams instead of one
+    launch per round step over all instances."""
     mats, keep = [], []
     for (T, N, nt, nn) in instances:
         m, k = _matrix_arg(T, N, nt, nn)
@@ -329,7 +333,8 @@ def pdfs_batch_create(instances, prune_mode="bound", device=0, autotune=False):
     arr = (pdfs_matrix * len(mats))(*mats)
     mode = PRUNE_MODES[prune_mode] if isinstance(prune_mode, str) else int(prune_mode)
     opt = pdfs_options(prune_mode=mode, device=device, stream=None,
-                       flags=PDFS_OPT_AUTOTUNE if autotune else 0)
+                       flags=(PDFS_OPT_AUTOTUNE if autotune else 0) |
+                       (PDFS_OPT_BATCH_STREAMS if streams_only else 0))
     out = ctypes.c_void_p()
     rc = lib.pdfs_batch_create(arr, len(mats), ctypes.byref(opt), ctypes.byref(out))
     del keep

@@ -31,11 +31,11 @@ def _compact(rounds):
     return [[*r["genes"], r["tp"], r["fp"], r["score_num"]] for r in rounds]
 
 
-def _batch(pdfs, idx, autotune=False, mode="bound"):
+def _batch(pdfs, idx, autotune=False, mode="bound", streams_only=False):
     insts = [synth.batched_instance(i) for i in idx]
     packed = [(I.packed(), I) for I in insts]
     b = pdfs.pdfs_batch_create([(T, N, I.n_tumor, I.n_normal) for (T, N), I in packed], mode,
-                               autotune=autotune)
+                               autotune=autotune, streams_only=streams_only)
     return b, insts
 
 
@@ -56,10 +56,14 @@ def test_batched_all_instances_match_oracle(pdfs):
     assert st["rounds"] == sum(len(gold[str(i)]["rounds"]) for i in range(32))
 
 
-def test_batched_autotune_and_empty_mode_same_results(pdfs):
+def test_batched_autotune_and_empty_mode_same_results(pdfs, tmp_path, monkeypatch):
+    """Tuned (work-item shape, seed size, split depth) and untuned batches give
+    the oracle's results; the tuner's choices land in its JSON cache."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("PDFS_TUNE_CACHE", str(cache))
     gold = _golden("batched")
-    idx = [0, 5, 7, 12, 14, 20, 24, 28]   # small instances: quick in empty mode too
-    for mode, tune in (("bound", True), ("empty", False)):
+    idx = [0, 5, 7, 10, 12, 16, 20, 24, 28]   # small instances: quick in empty mode too
+    for mode, tune in (("bound", True), ("empty", True), ("empty", False)):
         b, insts = _batch(pdfs, idx, autotune=tune, mode=mode)
         try:
             res, _ = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
@@ -68,6 +72,49 @@ def test_batched_autotune_and_empty_mode_same_results(pdfs):
             pdfs.pdfs_batch_destroy(b)
         for k, i in enumerate(idx):
             assert _compact(res[k]) == gold[str(i)]["rounds"], (mode, i)
+    entries = json.loads(cache.read_text())
+    assert entries and all(e["split"] in (2, 3) and e["chunk"] > 0 for e in entries)
+    assert {e["mode"] for e in entries} == {1, 2}
+
+
+@pytest.mark.parametrize("mode", ["bound", "empty"])
+def test_batched_streams_path_matches_oracle(pdfs, mode):
+    """The stream-parallel batched runs (each instance's own launches) give the
+    same results as the one-launch-per-step runs and the oracle."""
+    gold = _golden("batched")
+    idx = [2, 5, 12, 20]
+    b, insts = _batch(pdfs, idx, mode=mode, streams_only=True)
+    try:
+        res, _ = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
+                                     n_tumors=[I.n_tumor for I in insts])
+    finally:
+        pdfs.pdfs_batch_destroy(b)
+    for k, i in enumerate(idx):
+        assert _compact(res[k]) == gold[str(i)]["rounds"], (mode, i)
+
+
+def test_batched_empty_counters_equal_plain(pdfs):
+    """One launch per round step over several instances, empty-intersection
+    walk (two-phase depth 4 for the h = 4 ones): the summed per-depth counts
+    equal the plain path's on each instance alone, so every instance's walk
+    is complete and nothing is counted twice."""
+    idx = [0, 5, 10, 12, 16, 20]   # h = 3 and h = 4 (10, 16) cohorts
+    b, insts = _batch(pdfs, idx, mode="empty")
+    try:
+        res, st = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
+                                      n_tumors=[I.n_tumor for I in insts])
+    finally:
+        pdfs.pdfs_batch_destroy(b)
+    vis = [0] * 10
+    ne = [0] * 10
+    for k, I in enumerate(insts):
+        T, N = I.packed()
+        with pdfs.Solver(T, N, I.n_tumor, I.n_normal, "empty") as s:
+            plain, pst, _ = s.wsc(I.h, 1, 10)
+        assert _compact(res[k]) == _compact(plain), idx[k]
+        vis = [a + b for a, b in zip(vis, pst["visited"])]
+        ne = [a + b for a, b in zip(ne, pst["nonempty"])]
+    assert st["visited"] == vis and st["nonempty"] == ne
 
 
 def test_batched_equals_plain_path(pdfs):
