@@ -12,6 +12,14 @@ second of solve time, with the paper's empty-intersection pruning (the mode
 whose scored set is canonical).  The exact bound-pruned solve of the same
 workload (the library default) is timed beside it.
 
+Beside the step: the bound-pruned solve, whole solves of the two smaller
+workloads, the pruned-vs-exhaustive first rounds, deeper combinations, the
+held-out coverage report, the 32-instance batch (serial plain path, stream
+path, one launch per round step; bound and empty mode), the 2,000-request
+Poisson stream (served at 20 req/s, and served vs plain at a saturating
+rate), and the oracle on every host core (round 1 and the bound-pruned
+solve) as the CPU baseline.
+
 Prints one JSON line.  Run with --gpus 1 (the only supported count).
 """
 from __future__ import annotations
@@ -88,23 +96,106 @@ def dfs_alg_ops(st, h, n_normal, depth3_ops_per_word=4):
     return ops
 
 
-def cpu_baseline(inst, T, N, every=20):
-    """Oracle (single-threaded C, unmodified) on a bounded, stratified sample of
-    round 1: the search restricted to first genes at every `every`-th sorted
-    position.  Rate = leaves scored / seconds."""
+# ---- CPU baseline: the oracle (unmodified, pinned) on every host core.  The
+# outer loop of a round is cut into shares of first genes (the intervals of
+# Sec. III-D) handed to worker processes on request, as the paper's master
+# hands out work; the best of the shares under (S desc, tuple asc) is the
+# round's answer.
+_CPU = {}
+SHARE = 32           # first genes per share of the empty-mode round
+SHARE_BOUND = 512    # per share of a bound-pruned round (short rounds: fewer hand-offs)
+
+
+def _cpu_init(T, N, n_tumor, n_normal):
     from oracle import cpu
-    perm = cpu.order(T, N)
-    leaves = 0
-    t0 = time.perf_counter()
-    for g1 in range(0, inst.G, every):
-        b = cpu.best_share(T, N, inst.n_tumor, inst.n_normal, inst.h, inst.alpha_p,
-                           inst.alpha_q, g1, g1 + 1, perm=perm, mode="empty")
-        leaves += b.counters["nonempty"][inst.h]
-    dt = time.perf_counter() - t0
-    return {"value": leaves / dt, "unit": "subsets/s", "cores": 1, "kind": "oracle",
-            "sample": (f"round 1 of {inst.name}, empty-intersection walk, first gene at every "
-                       f"{every}th sorted position ({(inst.G + every - 1) // every} of {inst.G}); "
-                       f"{leaves} leaves in {dt:.1f} s")}
+    _CPU.update(T=T, N=N, nt=n_tumor, nn=n_normal, perm=cpu.order(T, N))
+
+
+def _cpu_share(args):
+    from oracle import cpu
+    import numpy as np
+    lo, hi, U, h, p, q, mode = args
+    b = cpu.best_share(_CPU["T"], _CPU["N"], _CPU["nt"], _CPU["nn"], h, p, q, lo, hi,
+                       U=np.asarray(U, dtype=np.uint64), mode=mode, perm=_CPU["perm"])
+    key = (b.score, [-i for i in b.sorted_idx]) if b.found else None
+    return key, b.sorted_idx, b.tp, b.fp, b.counters["nonempty"][h]
+
+
+def _cpu_round(pool, G, U, h, p, q, mode, firsts, share):
+    """One round over the first-gene shares [lo, lo + share) for lo in
+    `firsts`: (best key, sorted tuple, tp, fp), leaves scored."""
+    jobs = [(lo, min(lo + share, G), [int(x) for x in U], h, p, q, mode) for lo in firsts]
+    best, leaves = None, 0
+    for key, idx, tp, fp, ne in pool.imap_unordered(_cpu_share, jobs, chunksize=1):
+        leaves += ne
+        if key is not None and (best is None or key > best[0]):
+            best = (key, idx, tp, fp)
+    return best, leaves
+
+
+def cpu_baseline(inst, T, N, sample_every=4, full=False):
+    """The oracle on all host cores: the empty-mode walk of round 1 on a
+    stratified sample of first-gene shares (every `sample_every`-th; all of
+    them with full=True, median of 3), and the whole bound-pruned greedy
+    solve (median of 3).  value = round-1 leaves scored per second."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import cpu
+    cores = os.cpu_count() or 1
+    ctx = mp.get_context("spawn")
+    h, p, q = inst.h, inst.alpha_p, inst.alpha_q
+    U0 = cpu.full_mask(inst.n_tumor, T.shape[1])
+    with ctx.Pool(cores, initializer=_cpu_init, initargs=(T, N, inst.n_tumor, inst.n_normal)) as pool:
+        pool.map(_cpu_share, [(0, 1, [int(x) for x in U0], h, p, q, "empty")] * cores)  # warm
+        firsts = list(range(0, inst.G, SHARE))
+        sample = firsts if full else firsts[::sample_every]
+        reps = 3 if full else 1
+        rates = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            _, leaves = _cpu_round(pool, inst.G, U0, h, p, q, "empty", sample, SHARE)
+            dt = time.perf_counter() - t0
+            rates.append((leaves / dt, leaves, dt))
+            print(f"[bench] oracle round 1 sample: {leaves} leaves in {dt:.1f} s on {cores} cores",
+                  file=sys.stderr, flush=True)
+        rates.sort()
+        rate, leaves, dt = rates[len(rates) // 2]
+        # whole bound-pruned solve, round after round
+        perm = cpu.order(T, N)
+        solves = []
+        for _ in range(3):
+            U = U0.copy()
+            rounds = []
+            t0 = time.perf_counter()
+            covered = 0
+            target = inst.target_covered if inst.target_covered > 0 else inst.n_tumor
+            while covered < target:
+                best, _ = _cpu_round(pool, inst.G, U, h, p, q, "bound",
+                                     list(range(0, inst.G, SHARE_BOUND)), SHARE_BOUND)
+                if best is None:
+                    break
+                genes = [int(perm[i]) for i in best[1]]
+                cov = U.copy()
+                for g in genes:
+                    cov &= T[g]
+                U = U & ~cov
+                covered = inst.n_tumor - int(sum(bin(int(x)).count("1") for x in U))
+                rounds.append((genes, best[2], best[3]))
+            solves.append((time.perf_counter() - t0, rounds))
+            print(f"[bench] oracle bound solve: {len(rounds)} rounds in {solves[-1][0]:.2f} s",
+                  file=sys.stderr, flush=True)
+        solves.sort(key=lambda x: x[0])
+        solve_s, solve_rounds = solves[1]
+    frac = len(sample) / len(firsts)
+    return {"value": rate, "unit": "subsets/s", "cores": cores, "kind": "oracle",
+            "sample": (f"round 1 of {inst.name}, empty-intersection walk, first-gene shares of "
+                       f"{SHARE} sorted positions handed to {cores} worker processes on request; "
+                       f"{'all' if full else f'every {sample_every}th'} share ({frac:.2f} of the "
+                       f"round): {leaves} leaves in {dt:.1f} s" + (", median of 3" if full else "")),
+            "bound_solve_ms": 1e3 * solve_s, "bound_solve_rounds": len(solve_rounds),
+            "bound_solve": (f"whole bound-pruned greedy solve, shares of {SHARE_BOUND} first genes "
+                            f"per round, median of 3"),
+            "_rounds": solve_rounds}
 
 
 def _gen_request(j):
@@ -128,50 +219,86 @@ def _pool_map(fn, items):
         return pool.map(fn, items)
 
 
-def bench_batched(pdfs, data):
-    """32 instances: serially through the plain path vs one batched run."""
+def bench_batched(pdfs, data, modes=("bound", "empty")):
+    """32 instances: serially through the plain path, the stream path (each
+    instance's own launches on 4 streams) and one launch per round step over
+    all instances, in bound and empty mode (the batches tuned first)."""
     import torch
     hs = [d[5] for d in data]
-    # plain path: one context per instance, solved one after another
-    plain_ms = 0.0
-    plain_rounds = []
-    for (_, T, N, nt, nn, h) in data:
-        with pdfs.Solver(T, N, nt, nn, "bound") as s:
-            s.wsc(h, 1, 10)                        # warm (allocations)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            r, _, _ = s.wsc(h, 1, 10)
-            plain_ms += 1e3 * (time.perf_counter() - t)
-            plain_rounds.append([(x["genes"], x["tp"], x["fp"]) for x in r])
-    b = pdfs.pdfs_batch_create([(T, N, nt, nn) for (_, T, N, nt, nn, _) in data], "bound",
-                               autotune=True)
-    try:
-        ncap = [nt + 1 for (_, _, _, nt, _, _) in data]
-        pdfs.pdfs_batch_run(b, hs, 1, 10, n_tumors=ncap)   # warm + tune
-        times = []
-        for _ in range(3):
-            t = time.perf_counter()
-            res, st = pdfs.pdfs_batch_run(b, hs, 1, 10, n_tumors=ncap)
-            times.append(1e3 * (time.perf_counter() - t))
-    finally:
-        pdfs.pdfs_batch_destroy(b)
-    same = [[(x["genes"], x["tp"], x["fp"]) for x in r] for r in res] == plain_rounds
-    batched_ms = min(times)
-    return {"instances": 32, "plain_serial_ms": plain_ms, "batched_ms": batched_ms,
-            "speedup": plain_ms / batched_ms, "rounds": st["rounds"], "same_results": same,
-            "mode": "bound"}
+    ncap = [d[3] + 1 for d in data]
+    out = {"instances": len(data)}
+    for mode in modes:
+        plain_ms = 0.0
+        plain_rounds = []
+        for (_, T, N, nt, nn, h) in data:
+            with pdfs.Solver(T, N, nt, nn, mode) as s:
+                s.wsc(h, 1, 10)                        # warm (allocations)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r, _, _ = s.wsc(h, 1, 10)
+                plain_ms += 1e3 * (time.perf_counter() - t)
+                plain_rounds.append([(x["genes"], x["tp"], x["fp"]) for x in r])
+        row = {"plain_serial_ms": plain_ms}
+        reps = 3 if mode == "bound" else 1
+        for name, streams_only in (("streams", True), ("one_launch_per_step", False)):
+            b = pdfs.pdfs_batch_create([(T, N, nt, nn) for (_, T, N, nt, nn, _) in data], mode,
+                                       autotune=True, streams_only=streams_only)
+            try:
+                pdfs.pdfs_batch_run(b, hs, 1, 10, n_tumors=ncap)   # warm + tune
+                times = []
+                for _ in range(reps):
+                    t = time.perf_counter()
+                    res, st = pdfs.pdfs_batch_run(b, hs, 1, 10, n_tumors=ncap)
+                    times.append(1e3 * (time.perf_counter() - t))
+            finally:
+                pdfs.pdfs_batch_destroy(b)
+            same = [[(x["genes"], x["tp"], x["fp"]) for x in r] for r in res] == plain_rounds
+            row[name] = {"ms": min(times), "speedup_vs_plain_serial": plain_ms / min(times),
+                         "same_results": same, "rounds": st["rounds"]}
+            print(f"[bench] batched {mode} {name}: {min(times):.1f} ms vs plain serial "
+                  f"{plain_ms:.1f} ms", file=sys.stderr, flush=True)
+        out[mode] = row
+    return out
 
 
-def bench_served(pdfs, n_req, speed, data):
-    """The seeded Poisson request stream (mean 20 req/s, scaled by `speed`), h in
-    {2,3,4} at 3:5:2: continuous batching vs the plain path serving the same
-    arrivals one at a time."""
-    from paper_2603_16721_amd import synth
+def _pct(x, q):
     import numpy as np
-    arrivals = synth.served_arrivals()[:n_req] / speed
+    return float(np.percentile(np.asarray(x) * 1e3, q))
 
-    # plain path: one request at a time, in arrival order
-    lat_plain = []
+
+def _serve_stream(pdfs, data, arrivals, max_active=8):
+    """Submits each request at its arrival time to one server (continuous
+    batching) and polls until all are done: latencies and span."""
+    n_req = len(arrivals)
+    srv = pdfs.pdfs_server_create("bound", 0, 0, max_active)
+    lat = [None] * n_req
+    try:
+        tickets = []
+        t0 = time.perf_counter()
+        j = 0
+        pending = set()
+        while j < n_req or pending:
+            now = time.perf_counter() - t0
+            while j < n_req and arrivals[j] <= now:
+                (_, T, N, nt, nn, h) = data[j]
+                tickets.append(pdfs.pdfs_server_submit(srv, T, N, nt, nn, h, 1, 10))
+                pending.add(j)
+                j += 1
+            for k in list(pending):
+                r = pdfs.pdfs_server_poll(srv, tickets[k], cap=data[k][3] + 1)
+                if r is not None:
+                    lat[k] = r[1]
+                    pending.discard(k)
+            time.sleep(0.0005)
+        span = time.perf_counter() - t0
+    finally:
+        pdfs.pdfs_server_destroy(srv)
+    return lat, span
+
+
+def _plain_stream(pdfs, data, arrivals):
+    """The plain path serving the same arrivals one at a time."""
+    lat = []
     t0 = time.perf_counter()
     for j, (_, T, N, nt, nn, h) in enumerate(data):
         now = time.perf_counter() - t0
@@ -179,39 +306,66 @@ def bench_served(pdfs, n_req, speed, data):
             time.sleep(arrivals[j] - now)
         with pdfs.Solver(T, N, nt, nn, "bound") as s:
             s.wsc(h, 1, 10)
-        lat_plain.append(time.perf_counter() - t0 - arrivals[j])
-    span_plain = time.perf_counter() - t0
+        lat.append(time.perf_counter() - t0 - arrivals[j])
+    return lat, time.perf_counter() - t0
 
-    srv = pdfs.pdfs_server_create("bound", 0, 0, 8)
-    lat_srv = [None] * n_req
-    try:
-        tickets = []
-        t0 = time.perf_counter()
-        j = 0
-        while j < n_req or any(l is None for l in lat_srv):
-            now = time.perf_counter() - t0
-            while j < n_req and arrivals[j] <= now:
-                (_, T, N, nt, nn, h) = data[j]
-                tickets.append(pdfs.pdfs_server_submit(srv, T, N, nt, nn, h, 1, 10))
-                j += 1
-            for k, tk in enumerate(tickets):
-                if lat_srv[k] is None:
-                    r = pdfs.pdfs_server_poll(srv, tk, cap=data[k][3] + 1)
-                    if r is not None:
-                        lat_srv[k] = r[1]
-            time.sleep(0.0005)
-        span_srv = time.perf_counter() - t0
-    finally:
-        pdfs.pdfs_server_destroy(srv)
 
-    def pct(x, q):
-        return float(np.percentile(np.asarray(x) * 1e3, q))
-    return {"requests": n_req, "rate_req_per_s": 20.0 * speed,
-            "served": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99),
-                       "solves_per_s": n_req / span_srv},
-            "plain_one_at_a_time": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
-                                    "solves_per_s": n_req / span_plain},
-            "mode": "bound", "latency": "submission to result, seconds of wall time"}
+def bench_served(pdfs, data, saturate=20.0):
+    """The seeded Poisson request stream (mean 20 req/s), h in {2,3,4} at
+    3:5:2: continuous batching at the stream's own rate, and both the server
+    and the plain path (one request at a time) with the arrivals compressed
+    `saturate`-fold, where the arrival rate exceeds what either can serve."""
+    from paper_2603_16721_amd import synth
+    n_req = len(data)
+    arrivals = synth.served_arrivals()[:n_req]
+    lat, span = _serve_stream(pdfs, data, arrivals)
+    out = {"requests": n_req, "latency": "submission to result, wall time", "mode": "bound",
+           "at_20_req_per_s": {"served": {"p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+                                          "solves_per_s": n_req / span}}}
+    print(f"[bench] served at 20 req/s: p50 {_pct(lat, 50):.1f} ms, p99 {_pct(lat, 99):.1f} ms",
+          file=sys.stderr, flush=True)
+    fast = arrivals / saturate
+    lat_s, span_s = _serve_stream(pdfs, data, fast)
+    lat_p, span_p = _plain_stream(pdfs, data, fast)
+    out[f"at_{20 * saturate:g}_req_per_s"] = {
+        "served": {"p50_ms": _pct(lat_s, 50), "p99_ms": _pct(lat_s, 99),
+                   "solves_per_s": n_req / span_s},
+        "plain_one_at_a_time": {"p50_ms": _pct(lat_p, 50), "p99_ms": _pct(lat_p, 99),
+                                "solves_per_s": n_req / span_p}}
+    print(f"[bench] saturated ({20 * saturate:g} req/s): served {n_req / span_s:.1f} solves/s, "
+          f"plain {n_req / span_p:.1f} solves/s", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_small_solves(pdfs, stream):
+    """Whole greedy solves of the two smaller workloads (h2_G500, h3_G5000) in
+    both modes: solve time and subsets scored per second (empty mode)."""
+    import torch
+    from paper_2603_16721_amd import synth
+    out = {}
+    for name in ("h2_G500", "h3_G5000"):
+        wi = synth.WORKLOADS[name]()
+        Ti, Ni = wi.packed()
+        row = {}
+        for mode in ("empty", "bound"):
+            with pdfs.Solver(Ti, Ni, wi.n_tumor, wi.n_normal, mode, 0, stream) as sv:
+                sv.wsc(wi.h, wi.alpha_p, wi.alpha_q, target=wi.target_covered)
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(5):
+                    t = time.perf_counter()
+                    rr, st, _ = sv.wsc(wi.h, wi.alpha_p, wi.alpha_q, target=wi.target_covered)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t)
+            dt = sorted(ts)[2]
+            row[mode] = {"solve_ms": 1e3 * dt, "rounds": len(rr)}
+            if mode == "empty":
+                row[mode]["subsets_scored"] = st["nonempty"][wi.h]
+                row[mode]["subsets_scored_per_s"] = st["nonempty"][wi.h] / dt
+        out[name] = row
+        print(f"[bench] {name} solve: empty {row['empty']['solve_ms']:.2f} ms, bound "
+              f"{row['bound']['solve_ms']:.2f} ms", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -222,7 +376,13 @@ def main():
     ap.add_argument("--workload", default="h4_G20000")
     ap.add_argument("--bound-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-every", type=int, default=10)
+    ap.add_argument("--cpu-every", type=int, default=4,
+                    help="oracle baseline with --cpu-sample: every n-th first-gene share")
+    ap.add_argument("--cpu-sample", action="store_true",
+                    help="oracle baseline on a sample of round 1 (one pass) instead of the "
+                         "whole round (median of 3; ~10 s a pass on 16 cores)")
+    ap.add_argument("--no-small-solves", action="store_true",
+                    help="skip the whole solves of h2_G500 and h3_G5000")
     ap.add_argument("--no-bound", action="store_true",
                     help="skip the bound-pruning solve (profiling the empty-mode walk alone)")
     ap.add_argument("--no-batched", action="store_true")
@@ -233,9 +393,9 @@ def main():
                     help="skip the h = 5, 6 first-round report")
     ap.add_argument("--no-heldout", action="store_true",
                     help="skip the 75/25 held-out coverage report")
-    ap.add_argument("--served-requests", type=int, default=400)
-    ap.add_argument("--served-speed", type=float, default=1.0,
-                    help="arrival-rate multiplier of the 20 req/s stream")
+    ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--served-saturate", type=float, default=20.0,
+                    help="arrival-rate multiplier of the saturated pass")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; multi-GPU sharding of the search is not "
@@ -402,7 +562,7 @@ def main():
                   file=sys.stderr, flush=True)
 
     # ---- exact bound pruning (library default): solve time of the same workload
-    bound_ms, same = None, None
+    bound_ms, same, bound_rounds = None, None, None
     if not args.no_bound:
         svb = pdfs.Solver(Td, Nd, inst.n_tumor, inst.n_normal, "bound", 0, stream.cuda_stream)
         rb, _ = solve(svb)
@@ -415,6 +575,7 @@ def main():
         svb.close()
         same = [(r["genes"], r["tp"], r["fp"]) for r in rb2] == \
             [(r["genes"], r["tp"], r["fp"]) for r in rounds]
+        bound_rounds = [(r["genes"], r["tp"], r["fp"]) for r in rb2]
 
     out = {
         "metric": METRIC,
@@ -469,15 +630,22 @@ def main():
         out["deep_round1"] = deep
     if held is not None:
         out["heldout_75_25"] = held
+    if not args.no_small_solves:
+        out["small_solves"] = bench_small_solves(pdfs, stream.cuda_stream)
     if not args.no_batched:
         print("[bench] batched: 32 instances, plain serial vs batched", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(pdfs, data_b)
     if not args.no_served:
         print(f"[bench] served: {args.served_requests} requests", file=sys.stderr, flush=True)
-        out["served"] = bench_served(pdfs, args.served_requests, args.served_speed, data_s)
+        out["served"] = bench_served(pdfs, data_s, args.served_saturate)
     if not args.no_cpu_baseline:
-        print("[bench] timing the oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(inst, T, N, args.cpu_every)
+        print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
+        cb = cpu_baseline(inst, T, N, args.cpu_every, not args.cpu_sample)
+        rounds_cpu = cb.pop("_rounds")
+        if bound_rounds is not None:
+            cb["bound_solve_matches_gpu"] = rounds_cpu == bound_rounds
+        cb["gpu_bound_solve_speedup"] = (cb["bound_solve_ms"] / bound_ms) if bound_ms else None
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
