@@ -301,7 +301,7 @@ __device__ __forceinline__ void dfs_item(const Problem& P, const Work& w, RoundS
 // kBound: bound pruning (Sec. III-E) compiled in; the other modes run the
 // instantiation without it.
 template <int H, int W64, bool kBound>
-__global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
+__global__ __launch_bounds__(256, (W64 <= 6 || (W64 <= 8 && !kBound) ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
   // Narrow rows (<= 8 words): KG consecutive candidate rows arrive with one
   // 16-dword scalar load and are tested as a group, the next group in flight
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs(Problem P, Work
 // that instance its staged prefixes, best leaf and counts, and never returns
 // to it within the launch.
 template <int H, int W64, bool kBound>
-__global__ __launch_bounds__(256, (W64 <= 8 ? 3 : 2)) void k_dfs_multi(
+__global__ __launch_bounds__(256, (W64 <= 6 ? 3 : 2)) void k_dfs_multi(
     const BatchDesc* __restrict__ bd, BatchQueue* __restrict__ bq, int phase) {
   constexpr int W = 2 * W64;
   constexpr bool kNarrow = W <= 8;
