@@ -40,14 +40,15 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9          # lane-instructions/s (CUs x SIMDs x l
 MFMA_I8_PEAK_OPS = 5.0e15                 # dense int8 MFMA, ops/s (2 per multiply-add)
 
 # HBM traffic of the depth-first stage, per launch (one round), from two
-# rocprofv3 --pmc runs of one h4_G20000 solve (FETCH_SIZE, WRITE_SIZE), each
-# scaled by what the counter reads for a 1 GiB device copy (FETCH_SIZE reads
-# half the bytes, WRITE_SIZE all of them); profiles/dfs_stage_h4_G20000_traffic.md.
+# rocprofv3 --pmc runs of two h4_G20000 solves (FETCH_SIZE, WRITE_SIZE; KiB
+# summed over both solves' stage kernels), each scaled by what the counter
+# reads for a 1 GiB device copy (FETCH_SIZE reads half the bytes, WRITE_SIZE
+# all of them); profiles/dfs_stage_h4_G20000_traffic.md.
 # Valid for the stage kernels' sources it was taken on (hash below); reported
 # as null once they change.
 STAGE_SOURCES = ("k_dfs.hip", "k_tri.hip", "dfs_core.h", "slot_reduce.h", "pdfs_dev.h")
-STAGE_TRAFFIC = {"sources_sha256_16": "b290d0313d448d0f", "workload": "h4_G20000",
-                 "bytes_per_launch": (2.0 * 4155925 + 1.0 * 12869834) * 1024 / 133}
+STAGE_TRAFFIC = {"sources_sha256_16": "84848a9a3cbc6acb", "workload": "h4_G20000",
+                 "bytes_per_launch": (2.0 * 8292481 + 1.0 * 25292682) / 2 * 1024 / 133}
 
 
 def stage_traffic(workload):
