@@ -13,6 +13,37 @@ namespace {
 // held in SGPRs, used directly as VALU operands).
 typedef const __attribute__((address_space(4))) uint32_t cu32;
 
+// A launch's problem and workspace where a kernel reads them again: its own
+// arguments (through the kernel-argument segment) or a batch descriptor,
+// both unchanged while it runs, so read through the constant address space.
+typedef const __attribute__((address_space(4))) Problem cProblem;
+typedef const __attribute__((address_space(4))) Work cWork;
+
+// p, opaque to the optimiser: loads through the result are made where they
+// are written instead of being hoisted out of loops and held in scalar
+// registers (or spilled) across them.
+template <class T>
+__device__ __forceinline__ T* fresh(T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// *p by 32-bit words (scalar loads; the words of fields left unused are
+// never loaded).
+template <class T>
+__device__ __forceinline__ T load_const(const __attribute__((address_space(4))) T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+  union {
+    T t;
+    uint32_t u[sizeof(T) / 4];
+  } r;
+  const __attribute__((address_space(4))) uint32_t* s =
+      (const __attribute__((address_space(4))) uint32_t*)p;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) r.u[i] = s[i];
+  return r.t;
+}
+
 // d = (a & b) | c with b a wave-uniform (SGPR) operand.
 __device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t b, uint32_t c) {
   uint32_t d;
@@ -46,16 +77,15 @@ __device__ __forceinline__ uint32_t fold_nonempty(const uint32_t (&y)[W], cu32* 
   return a0 | a1 | a2 | a3;
 }
 
-// OR over k of (y[k] & r[k]) for a row already in (scalar) registers.
+// OR over k of (y[k] & r[k]) for a row already in (scalar) registers, as one
+// dependent chain (W operations; a wave's dependent VALU operations issue
+// back to back).
 template <int W>
-__device__ __forceinline__ uint32_t fold_nonempty_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
-  uint32_t a0 = 0, a1 = 0;
+__device__ __forceinline__ uint32_t fold_chain_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
+  uint32_t a = y[0] & r[0];
 #pragma unroll
-  for (int k = 0; k < W; k += 2) {
-    a0 = and_or(y[k], r[k], a0);
-    if (k + 1 < W) a1 = and_or(y[k + 1], r[k + 1], a1);
-  }
-  return a0 | a1;
+  for (int k = 1; k < W; ++k) a = and_or(y[k], r[k], a);
+  return a;
 }
 
 // sum over k of popcount(y[k] & row[k]), four accumulator chains.
@@ -203,6 +233,12 @@ struct Tally {
   unsigned long long xv3, xv4, xfp;   // active-candidate visits, FP-counted leaves
   __device__ void init() { ne3 = ne4 = vis3 = vis4 = bp2 = bp3 = xv3 = xv4 = xfp = 0; }
 };
+
+// base + the number of lanes below this one whose bit is set in m.
+__device__ __forceinline__ int rank_below(unsigned long long m, int base) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)base));
+}
 
 // Largest v over the wave.
 __device__ __forceinline__ int wave_max(int v) {

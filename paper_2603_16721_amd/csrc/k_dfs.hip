@@ -78,7 +78,6 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
 struct DfsView {
   const unsigned long long* plist;   // phase 1: the seed list, 2: the work list
   unsigned long long npairs;
-  const __attribute__((address_space(4))) Item* items;
   int nA_all;
   int c_long;       // c < c_long: at least w.long_stream depth-4 candidates
   bool all_pre;     // exhaustive mode (h = 4): every depth-3 prefix is extended
@@ -91,7 +90,6 @@ __device__ __forceinline__ DfsView dfs_view(const Problem& P, const Work& w, con
   DfsView v;
   v.plist = phase == 1 ? w.seed_pairs : w.work_pairs;
   v.npairs = phase == 1 ? (st->n_seed < kSeedCap ? st->n_seed : kSeedCap) : st->n_work_pairs;
-  v.items = (const __attribute__((address_space(4))) Item*)w.items;
   v.nA_all = uniform(st->nA);
   v.c_long = v.nA_all - w.long_stream;
   v.all_pre = H == 4 && P.mode == kPruneNone;
@@ -102,31 +100,38 @@ __device__ __forceinline__ DfsView dfs_view(const Problem& P, const Work& w, con
   return v;
 }
 
-// One work item: 64 pairs (one per lane) x the depth-3 candidates [c_lo,
-// c_hi), each non-empty depth-3 prefix scored (h = 3), listed or queued and
-// expanded at depth 4 (h = 4).
+// One walk: the 64 pairs of a batch (one per lane) x the depth-3 candidates
+// [c_lo, c_hi) -- one work item, or a run of consecutive items of the batch
+// -- each non-empty depth-3 prefix scored (h = 3), listed or queued and
+// expanded at depth 4 (h = 4).  first_chunk: the range starts at the batch's
+// first candidate (its pair-level counts are taken there).
+//
+// Pp, wp: where the instance's problem and workspace are read (the kernel's
+// arguments or its batch descriptor).  They are read at the item's start and
+// again for every depth-4 pass or append, so the walk holds only what it
+// uses in scalar registers.
 template <int H, int W64, bool kBound>
-__device__ __forceinline__ void dfs_item(const Problem& P, const Work& w, RoundState* st,
-                                         const DfsView& v, uint32_t it, uint32_t* q,
-                                         unsigned long long* sq, int& sn, Best& best, Tally& tl,
-                                         unsigned long long& inc, int lane) {
+__device__ __forceinline__ void dfs_item(cProblem* Pp, cWork* wp, int phase, uint32_t batch,
+                                         int c_lo, int c_hi, uint32_t first_chunk,
+                                         uint32_t* q, unsigned long long* sq, int& sn,
+                                         Best& best, Tally& tl, unsigned long long& inc,
+                                         int lane) {
   constexpr int W = 2 * W64;
-  constexpr bool kNarrow = W <= 8;
-  constexpr int KG = kNarrow ? 16 / W : 1;
+  constexpr bool kPipe = W <= 16;
+  constexpr int KG = W <= 8 ? 16 / W : 1;
+  const Problem P = load_const(fresh(Pp));
+  const Work w = load_const(fresh(wp));
+  RoundState* st = w.st;
+  const DfsView v = dfs_view<H>(P, w, st, phase);
   const unsigned long long* __restrict__ plist = v.plist;
   const unsigned long long npairs = v.npairs;
-  const auto items = v.items;
   const int nA_all = v.nA_all;
   const int c_long = v.c_long;
   const bool all_pre = v.all_pre;
   const bool list_long = v.list_long;
   cu32* TA = (cu32*)w.TA;
   cu32* NA = (cu32*)w.NA;
-  const int c_lo = uniform((int)items[it].c_lo);
-  const int c_hi = uniform((int)items[it].c_hi);
   if (c_lo >= c_hi) return;   // never made by the item builder
-  const uint32_t batch = (uint32_t)uniform((int)items[it].batch);
-  const uint32_t first_chunk = (uint32_t)uniform((int)items[it].pad) & 1u;
   const unsigned long long pi = (unsigned long long)batch * kPairBatch + lane;
   bool valid = pi < npairs;
   const unsigned long long e = valid ? plist[pi] : 0ull;
@@ -166,15 +171,19 @@ __device__ __forceinline__ void dfs_item(const Problem& P, const Work& w, RoundS
   int qn = 0;
   // Non-empty depth-3 prefixes (lane, c) of candidate c, m = their lanes:
   // scored (h = 3), or bound-tested and then listed or queued (h = 4).
-  // mq = the prefixes to extend: m, or every (lane, c) in exhaustive mode
-  auto on_hits = [&](int c, unsigned long long m, unsigned long long mq) {
-    bool hit = (m >> lane) & 1ull;
+  // m_hit: the lanes whose (lane, c) is non-empty; m: the prefixes to
+  // extend -- the non-empty ones, or every (lane, c) in exhaustive mode.
+  // Lane flags are taken from the masks as they are (inverse ballot), and a
+  // lane's slot in a queue is its rank among the wave's extended prefixes
+  // (mbcnt).
+  const unsigned long long valid_m = __ballot(valid);
+  const int b_max = wave_max(valid ? b : -1);   // c > b_max: every valid lane takes c
+  const unsigned long long ab_entry = triple_entry(a, b, 0);
+  uint32_t ne3 = 0;   // this item's non-empty depth-3 prefixes (< 64 * 65536)
+  auto on_hits = [&](int c, unsigned long long m_hit, unsigned long long m) {
     cu32* row = TA + (size_t)c * W;
-    tl.ne3 += __popcll(m);
-    if (all_pre) {
-      hit = (mq >> lane) & 1ull;
-      m = mq;
-    }
+    ne3 += (uint32_t)__popcll(m_hit);
+    bool hit = __builtin_amdgcn_inverse_ballot_w64(m);
     if (H == 3) {
       int fp = 0;
       const bool zn = znz != 0 || P.tn_literal;
@@ -209,15 +218,14 @@ __device__ __forceinline__ void dfs_item(const Problem& P, const Work& w, RoundS
       m = __ballot(hit);
       if (m == 0) return;
     }
+    const int r = rank_below(m, 0);
     if (list_long && c < c_long) {
-      const int sp = sn + __popcll(m & ((1ull << lane) - 1));
-      if (hit) sq[sp] = triple_entry(a, b, c);
+      if (hit) sq[sn + r] = ab_entry | ((unsigned long long)c << 32);
       sn += __popcll(m);
       wave_lds_sync();
       return;
     }
-    const int pos = qn + __popcll(m & ((1ull << lane) - 1));
-    if (hit) q[pos] = (uint32_t)lane | ((uint32_t)c << 6);
+    if (hit) q[qn + r] = (uint32_t)lane | ((uint32_t)c << 6);
     qn += __popcll(m);
     wave_lds_sync();
   };
@@ -225,13 +233,16 @@ __device__ __forceinline__ void dfs_item(const Problem& P, const Work& w, RoundS
   // wave of queued prefixes becomes a depth-4 pass.
   auto drain = [&]() {
     if (H != 4) return;
+    if (sn < kStage && qn < kWave) return;
+    const Problem P2 = load_const(fresh(Pp));
+    const Work w2 = load_const(fresh(wp));
     if (sn >= kStage) {
-      append_staged(w, st, sq, sn, lane);
+      append_staged(w2, w2.st, sq, sn, lane);
       sn = 0;
     }
     int off = 0;
     while (qn - off >= kWave) {
-      depth4<W, kBound>(P, w, st, q + off, kWave, y2, z2, a, b, best, tl, inc, lane);
+      depth4<W, kBound>(P2, w2, w2.st, q + off, kWave, y2, z2, a, b, best, tl, inc, lane);
       off += kWave;
     }
     if (off > 0) {
@@ -243,86 +254,116 @@ __device__ __forceinline__ void dfs_item(const Problem& P, const Work& w, RoundS
       qn = rest;
     }
   };
-  if (!kNarrow) {
-    for (int c = c_lo; c < c_hi; ++c) {
-      const uint32_t acc = fold_nonempty<W>(y2, TA + (size_t)c * W);
-      const unsigned long long m = __ballot(valid && c > b && acc != 0);
-      const unsigned long long mq = all_pre ? __ballot(valid && c > b) : m;
-      if (mq == 0) continue;
-      on_hits(c, m, mq);
-      drain();
-    }
-  } else {
-    // rows past c_hi are loaded (inside the round's row allocation: at
-    // least 128 rows past the last active one) but never tested
-    const unsigned long long valid_m = __ballot(valid);
-    auto group = [&](int c0, const uint32_t (&rows)[KG][W]) {
-      unsigned long long m[KG], mq[KG];
-      unsigned long long any = 0;
-#pragma unroll
-      for (int j = 0; j < KG; ++j) {
-        const uint32_t acc = fold_nonempty_r<W>(y2, rows[j]);
-        const unsigned long long in = c0 + j < c_hi ? __ballot(c0 + j > b) & valid_m : 0ull;
-        m[j] = __ballot(acc != 0) & in;
-        mq[j] = all_pre ? in : m[j];
-        any |= mq[j];
+  // The walk stops as soon as a full wave of prefixes is queued or the
+  // staging buffer is full; the depth-4 passes and the append run outside
+  // it and the walk resumes at the next candidate.  So no candidate rows in
+  // flight (nor the walk's lane masks) stay live across a depth-4 pass,
+  // whose own row buffers then fit the scalar registers.
+  auto full = [&]() { return H == 4 && (qn >= kWave || sn >= kStage); };
+  int c = c_lo;
+  while (c < c_hi) {
+    if (!kPipe) {
+      while (c < c_hi) {
+        const uint32_t acc = fold_nonempty<W>(y2, TA + (size_t)c * W);
+        unsigned long long m_in = valid_m;
+        if (c <= b_max) m_in &= __ballot(c > b);
+        const unsigned long long m_hit = __ballot(acc != 0) & m_in;
+        const unsigned long long m = all_pre ? m_in : m_hit;
+        const int cc = c++;
+        if (m == 0) continue;
+        on_hits(cc, m_hit, m);
+        if (full()) break;
       }
-      if (any == 0) return;
+    } else {
+      // Rows past c_hi are loaded (inside the round's row allocation: at
+      // least 128 rows past the last active one) but never tested.  Each
+      // row of a group is tested and acted on before the next, so only one
+      // row's lane masks are live.
+      auto group = [&](int c0, const uint32_t (&rows)[KG][W]) {
 #pragma unroll
-      for (int j = 0; j < KG; ++j)
-        if (mq[j]) on_hits(c0 + j, m[j], mq[j]);
-      drain();
-    };
-    constexpr int kNoClamp = 0x7fffffff;
-    uint32_t rA[KG][W], rB[KG][W];
-    int c0 = c_lo;
-    load_rows<W, KG>(rA, TA, c0, kNoClamp);
-    for (;;) {
-      int cn = c0 + KG;
-      after_arrival<W, KG>(cn, rA);
-      load_rows<W, KG>(rB, TA, cn, kNoClamp);
-      group(c0, rA);
-      c0 += KG;
-      if (c0 >= c_hi) break;
-      cn = c0 + KG;
-      after_arrival<W, KG>(cn, rB);
-      load_rows<W, KG>(rA, TA, cn, kNoClamp);
-      group(c0, rB);
-      c0 += KG;
-      if (c0 >= c_hi) break;
+        for (int j = 0; j < KG; ++j) {
+          const int cj = c0 + j;
+          if (cj >= c_hi) break;
+          const uint32_t acc = fold_chain_r<W>(y2, rows[j]);
+          unsigned long long m_in = valid_m;
+          if (cj <= b_max) m_in &= __ballot(cj > b);
+          const unsigned long long m_hit = __ballot(acc != 0) & m_in;
+          const unsigned long long m = all_pre ? m_in : m_hit;
+          if (m) on_hits(cj, m_hit, m);
+        }
+      };
+      constexpr int kNoClamp = 0x7fffffff;
+      uint32_t rA[KG][W], rB[KG][W];
+      load_rows<W, KG>(rA, TA, c, kNoClamp);
+      for (;;) {
+        int cn = c + KG;
+        after_arrival<W, KG>(cn, rA);
+        load_rows<W, KG>(rB, TA, cn, kNoClamp);
+        group(c, rA);
+        c += KG;
+        if (c >= c_hi || full()) break;
+        cn = c + KG;
+        after_arrival<W, KG>(cn, rB);
+        load_rows<W, KG>(rA, TA, cn, kNoClamp);
+        group(c, rB);
+        c += KG;
+        if (c >= c_hi || full()) break;
+      }
     }
+    drain();
   }
   if (H == 4 && qn > 0) {
-    depth4<W, kBound>(P, w, st, q, qn, y2, z2, a, b, best, tl, inc, lane);
+    const Problem P2 = load_const(fresh(Pp));
+    const Work w2 = load_const(fresh(wp));
+    depth4<W, kBound>(P2, w2, w2.st, q, qn, y2, z2, a, b, best, tl, inc, lane);
     qn = 0;
   }
+  tl.ne3 += ne3;
 }
 
 // kBound: bound pruning (Sec. III-E) compiled in; the other modes run the
 // instantiation without it.
+constexpr unsigned long long kGuide = 4;   // a run: 1/kGuide of a wave's share of the rest
+constexpr unsigned long long kMaxRun = 4;   // items per cursor step at most
+
+// The argument layout of k_dfs in its kernel-argument segment (in order,
+// each at its natural alignment).
+struct DfsArgs {
+  Problem P;
+  Work w;
+  int phase;
+};
+
 template <int H, int W64, bool kBound>
 __global__ __launch_bounds__(256, (W64 <= 6 || (W64 <= 8 && !kBound) ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
-  // Narrow rows (<= 8 words): KG consecutive candidate rows arrive with one
-  // 16-dword scalar load and are tested as a group, the next group in flight
-  // while the current one is tested; their prefixes are queued before any
-  // depth-4 pass, so the queues hold up to KG more waves' worth.  (Wider
-  // rows one at a time: a double-buffered single row measured 13 % slower at
-  // 16 words.)
-  constexpr bool kNarrow = W <= 8;
-  constexpr int KG = kNarrow ? 16 / W : 1;
+  // Rows of up to 8 words: candidate rows arrive in groups of KG (one
+  // 16-dword scalar load for up to 4 words, one row above that), the next
+  // group in flight while the current one is tested; a group's prefixes are
+  // queued before any depth-4 pass, so the queues hold up to KG more waves'
+  // worth.  (Wider rows one at a time: a double-buffered row measured 13 %
+  // slower at 16 words.)
+  constexpr int KG = W <= 8 ? 16 / W : 1;
   __shared__ uint32_t qbuf[kBlock / kWave][kWave * (KG + 1)];
   // h = 4, two-phase: staged long-stream prefixes before a global append
   __shared__ unsigned long long sbuf[kBlock / kWave][H == 4 ? kStage + KG * kWave : 1];
   RoundState* st = w.st;
   if (st->done) return;
+  const auto* args = (const __attribute__((address_space(4))) DfsArgs*)
+      __builtin_amdgcn_kernarg_segment_ptr();
+  cProblem* Pp = &args->P;
+  cWork* wp = &args->w;
+  // the arguments read back through the segment must be the ones passed
+  if (fresh(wp)->st != st || fresh(Pp)->G != P.G || fresh(wp)->TA != w.TA) {
+    if (threadIdx.x == 0) atomicOr(&st->overflow, 2);
+    return;
+  }
   const int lane = threadIdx.x & 63;
-  const int wib = threadIdx.x >> 6;
+  const int wib = uniform(threadIdx.x >> 6);
   uint32_t* q = qbuf[wib];
   unsigned long long* sq = sbuf[wib];
   int sn = 0;
   // phase 1 expands the seed list, phase 2 the (filtered) work list
-  const DfsView view = dfs_view<H>(P, w, st, phase);
   const unsigned long long nit = st->n_items;
   const uint32_t nitems = (uint32_t)uniform((int)(nit < w.item_cap ? nit : w.item_cap));
   if (blockIdx.x == 0 && threadIdx.x == 0 && nit > w.item_cap) st->overflow |= 1;
@@ -336,27 +377,47 @@ __global__ __launch_bounds__(256, (W64 <= 6 || (W64 <= 8 && !kBound) ? 3 : 2)) v
   // Scheduling: the grid is sized to what the device holds at once, so every
   // wave starts at launch.  Wave g takes item g first (no atomic at launch);
   // further items come from a shared cursor that counts past the first
-  // nwaves.  A plain read first, so that once the items are gone waves leave
-  // without queueing on the cursor's atomic.
+  // nwaves, in runs of consecutive items whose length follows the work left
+  // (guided self-scheduling: about 1/kGuide of a wave's share of the rest,
+  // at most kMaxRun), so that the cursor's atomics -- which one address
+  // serves one at a time -- stay far fewer than the items, while the last
+  // runs are single items.  A plain read first, so that once the items are
+  // gone waves leave without queueing on the atomic.  Consecutive items of
+  // one batch in a run are walked as one range.
+  const auto* items = (const __attribute__((address_space(4))) Item*)w.items;
   const uint32_t nwaves = gridDim.x * (kBlock / kWave);
   const uint32_t gw = blockIdx.x * (kBlock / kWave) + wib;
-  bool first = true;
+  uint32_t t_next = gw, t_end = gw + 1;
   for (;;) {
-    uint32_t it = nitems;
-    if (first) {
-      it = gw;
-      first = false;
-    } else if (lane == 0) {
-      const unsigned long long cur =
-          __hip_atomic_load(&st->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (cur + nwaves < nitems)
-        it = (uint32_t)(nwaves + atomicAdd(&st->cursor, 1ull));
+    if (t_next >= t_end) {
+      uint32_t start = nitems, cnt = 1;
+      if (lane == 0) {
+        const unsigned long long cur =
+            __hip_atomic_load(&st->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur + nwaves < nitems) {
+          const unsigned long long left = nitems - nwaves - cur;
+          const unsigned long long run = left / (kGuide * (unsigned long long)nwaves);
+          cnt = run < 1 ? 1u : (run > kMaxRun ? (uint32_t)kMaxRun : (uint32_t)run);
+          start = (uint32_t)(nwaves + atomicAdd(&st->cursor, (unsigned long long)cnt));
+        }
+      }
+      t_next = (uint32_t)uniform((int)start);
+      t_end = t_next + (uint32_t)uniform((int)cnt);
+      if (t_end > nitems) t_end = nitems;
     }
-    it = (uint32_t)uniform((int)it);
-    if (it >= nitems) break;
-    dfs_item<H, W64, kBound>(P, w, st, view, it, q, sq, sn, best, tl, inc, lane);
+    if (t_next >= nitems) break;
+    // the longest same-batch stretch of the run from t_next
+    const uint32_t batch = (uint32_t)uniform((int)items[t_next].batch);
+    uint32_t t_last = t_next;
+    while (t_last + 1 < t_end && (uint32_t)uniform((int)items[t_last + 1].batch) == batch) ++t_last;
+    const int c_lo = uniform((int)items[t_next].c_lo);
+    const int c_hi = uniform((int)items[t_last].c_hi);
+    const uint32_t first_chunk = (uint32_t)uniform((int)items[t_next].pad) & 1u;
+    t_next = t_last + 1;
+    dfs_item<H, W64, kBound>(Pp, wp, phase, batch, c_lo, c_hi, first_chunk, q, sq, sn, best,
+                             tl, inc, lane);
   }
-  if (H == 4 && sn > 0) append_staged(w, st, sq, sn, lane);
+  if (H == 4 && sn > 0) append_staged(load_const(fresh(wp)), st, sq, sn, lane);
 
   // block argmax -> slot
   Slot sl = empty_slot();
@@ -398,26 +459,26 @@ template <int H, int W64, bool kBound>
 __global__ __launch_bounds__(256, (W64 <= 6 ? 3 : 2)) void k_dfs_multi(
     const BatchDesc* __restrict__ bd, BatchQueue* __restrict__ bq, int phase) {
   constexpr int W = 2 * W64;
-  constexpr bool kNarrow = W <= 8;
-  constexpr int KG = kNarrow ? 16 / W : 1;
+  constexpr int KG = W <= 8 ? 16 / W : 1;
   __shared__ uint32_t qbuf[kBlock / kWave][kWave * (KG + 1)];
   __shared__ unsigned long long sbuf[kBlock / kWave][H == 4 ? kStage + KG * kWave : 1];
   const int lane = threadIdx.x & 63;
-  const int wib = threadIdx.x >> 6;
+  const int wib = uniform(threadIdx.x >> 6);
   uint32_t* q = qbuf[wib];
   unsigned long long* sq = sbuf[wib];
   int sn = 0;
   const uint32_t total = (uint32_t)uniform((int)bq->total);
   int cur = -1;
   uint32_t lo = 0, hi = 0;
-  Problem P;
-  Work w;
-  RoundState* st = nullptr;
-  DfsView view;
+  const auto* cbd = (const __attribute__((address_space(4))) BatchDesc*)bd;
+  cProblem* Pp = nullptr;
+  cWork* wp = nullptr;
   Best best;
   Tally tl;
   unsigned long long inc = 0;
   auto flush = [&]() {
+    const Work w = load_const(fresh(wp));
+    RoundState* st = w.st;
     if (H == 4 && sn > 0) {
       append_staged(w, st, sq, sn, lane);
       sn = 0;
@@ -465,15 +526,20 @@ __global__ __launch_bounds__(256, (W64 <= 6 ? 3 : 2)) void k_dfs_multi(
       cur = i;
       lo = (uint32_t)uniform((int)bq->base[i]);
       hi = (uint32_t)uniform((int)bq->base[i + 1]);
-      P = bd[i].P;
-      w = bd[i].w;
-      st = w.st;
-      view = dfs_view<H>(P, w, st, phase);
+      Pp = &cbd[i].P;
+      wp = &cbd[i].w;
       best.init();
       tl.init();
       inc = 0;
     }
-    dfs_item<H, W64, kBound>(P, w, st, view, g - lo, q, sq, sn, best, tl, inc, lane);
+    {
+      const auto* items = (const __attribute__((address_space(4))) Item*)fresh(wp)->items;
+      const uint32_t it = g - lo;
+      dfs_item<H, W64, kBound>(Pp, wp, phase, (uint32_t)uniform((int)items[it].batch),
+                               uniform((int)items[it].c_lo), uniform((int)items[it].c_hi),
+                               (uint32_t)uniform((int)items[it].pad) & 1u, q, sq, sn, best, tl,
+                               inc, lane);
+    }
   }
   if (cur >= 0) flush();
 }
