@@ -375,37 +375,62 @@ __global__ __launch_bounds__(256, (W64 <= 6 || (W64 <= 8 && !kBound) ? 3 : 2)) v
   unsigned long long inc = 0;
 
   // Scheduling: the grid is sized to what the device holds at once, so every
-  // wave starts at launch.  Wave g takes item g first (no atomic at launch);
-  // further items come from a shared cursor that counts past the first
-  // nwaves, in runs of consecutive items whose length follows the work left
-  // (guided self-scheduling: about 1/kGuide of a wave's share of the rest,
-  // at most kMaxRun), so that the cursor's atomics -- which one address
-  // serves one at a time -- stay far fewer than the items, while the last
-  // runs are single items.  A plain read first, so that once the items are
-  // gone waves leave without queueing on the atomic.  Consecutive items of
-  // one batch in a run are walked as one range.
+  // wave starts at launch.  The items are split into kSubQueues contiguous
+  // ranges, each with its own cursor (256 bytes apart, so that the atomics
+  // of different ranges do not queue on one address -- one address serves
+  // its atomics one at a time).  Wave g belongs to range g % kSubQueues: it
+  // takes its first item there without an atomic, then runs of consecutive
+  // items from that range's cursor (guided self-scheduling: about 1/kGuide
+  // of a wave's share of what is left in the range, at most kMaxRun), and
+  // once the range is done, runs from the following ranges in turn; it
+  // leaves when every range is done.  A plain read before each atomic, so
+  // that a done range costs no atomic.  Consecutive items of one batch in a
+  // run are walked as one range of candidates.
   const auto* items = (const __attribute__((address_space(4))) Item*)w.items;
   const uint32_t nwaves = gridDim.x * (kBlock / kWave);
   const uint32_t gw = blockIdx.x * (kBlock / kWave) + wib;
-  uint32_t t_next = gw, t_end = gw + 1;
+  auto range_lo = [&](uint32_t r) {
+    return (uint32_t)((unsigned long long)nitems * r / kSubQueues);
+  };
+  // waves g with g % kSubQueues == r
+  auto range_waves = [&](uint32_t r) { return (nwaves + kSubQueues - 1 - r) / kSubQueues; };
+  uint32_t qs = gw % kSubQueues;
+  uint32_t q_left = kSubQueues;   // ranges not yet found done
+  uint32_t t_next = range_lo(qs) + gw / kSubQueues;
+  uint32_t t_end = t_next + 1;
+  if (t_end > range_lo(qs + 1)) t_end = t_next;   // the range has fewer items than waves
   for (;;) {
     if (t_next >= t_end) {
-      uint32_t start = nitems, cnt = 1;
-      if (lane == 0) {
-        const unsigned long long cur =
-            __hip_atomic_load(&st->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur + nwaves < nitems) {
-          const unsigned long long left = nitems - nwaves - cur;
-          const unsigned long long run = left / (kGuide * (unsigned long long)nwaves);
-          cnt = run < 1 ? 1u : (run > kMaxRun ? (uint32_t)kMaxRun : (uint32_t)run);
-          start = (uint32_t)(nwaves + atomicAdd(&st->cursor, (unsigned long long)cnt));
+      uint32_t start = 0, cnt = 0;
+      while (q_left > 0) {
+        const uint32_t hi = range_lo(qs + 1);
+        const uint32_t nw = range_waves(qs);
+        const uint32_t base = range_lo(qs) + nw;
+        if (lane == 0) {
+          unsigned long long* cur_p = w.cursors + (size_t)qs * kCursorStride;
+          const unsigned long long cur =
+              __hip_atomic_load(cur_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (base + cur < hi) {
+            const unsigned long long left = hi - base - cur;
+            const unsigned long long run = left / (kGuide * (unsigned long long)(nw > 0 ? nw : 1));
+            cnt = run < 1 ? 1u : (run > kMaxRun ? (uint32_t)kMaxRun : (uint32_t)run);
+            start = (uint32_t)(base + atomicAdd(cur_p, (unsigned long long)cnt));
+          }
         }
+        start = (uint32_t)uniform((int)start);
+        cnt = (uint32_t)uniform((int)cnt);
+        if (cnt > 0 && start < hi) {
+          if (start + cnt > hi) cnt = hi - start;
+          break;
+        }
+        cnt = 0;
+        qs = qs + 1 == kSubQueues ? 0 : qs + 1;
+        --q_left;
       }
-      t_next = (uint32_t)uniform((int)start);
-      t_end = t_next + (uint32_t)uniform((int)cnt);
-      if (t_end > nitems) t_end = nitems;
+      if (cnt == 0) break;
+      t_next = start;
+      t_end = start + cnt;
     }
-    if (t_next >= nitems) break;
     // the longest same-batch stretch of the run from t_next
     const uint32_t batch = (uint32_t)uniform((int)items[t_next].batch);
     uint32_t t_last = t_next;
@@ -594,6 +619,8 @@ __device__ __forceinline__ void make_items_body(const Problem& P, const Work& w,
   if (st->done) return;
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // the walk's range cursors start from zero (this kernel runs before every walk)
+  if (blockIdx.x == 0 && threadIdx.x < kSubQueues) w.cursors[threadIdx.x * kCursorStride] = 0ull;
   const unsigned long long* __restrict__ list = seed ? w.seed_pairs : w.work_pairs;
   const unsigned long long np =
       seed ? (st->n_seed < kSeedCap ? st->n_seed : kSeedCap) : st->n_work_pairs;

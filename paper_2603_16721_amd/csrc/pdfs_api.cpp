@@ -55,7 +55,7 @@ hipError_t dalloc(pdfs_ctx* c, T** p, size_t n) {
 
 void release(pdfs_ctx* c) {
   void* ptrs[] = {c->Ts, c->Ns, c->perm, c->ncount, c->U, c->cols, c->act, c->flags, c->TA, c->NA,
-                  c->A8, c->N8, c->pairs, c->work_pairs, c->seed_pairs, c->hist,
+                  c->A8, c->N8, c->pairs, c->work_pairs, c->seed_pairs, c->hist, c->cursors,
                   c->items, c->slots, c->tallies, c->st, c->recs, c->tri, c->tri_s,
                   c->c_hist, c->deepq};
   for (void* p : ptrs) dfree(c, p);
@@ -149,6 +149,7 @@ Work make_work(pdfs_ctx* c, int w64, int target) {
   w.pairs = c->pairs;
   w.work_pairs = (c->prune_mode == PDFS_PRUNE_BOUND && c->work_pairs) ? c->work_pairs : c->pairs;
   w.seed_pairs = c->seed_pairs; w.hist = c->hist; w.items = c->items; w.slots = c->slots;
+  w.cursors = c->cursors;
   w.tallies = c->tallies;
   w.st = c->st; w.recs = c->recs; w.rec_cap = c->rec_cap;
   w.pair_cap = c->pair_cap; w.item_cap = c->item_cap;
@@ -827,6 +828,7 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   CKC(dalloc(c, &c->recs, (size_t)c->rec_cap));
   CKC(dalloc(c, &c->slots, (size_t)kSlotPhases * kSlotsPerPhase));
   CKC(dalloc(c, &c->hist, (size_t)kMaxCount + 1));
+  CKC(dalloc(c, &c->cursors, (size_t)kSubQueues * kCursorStride));
   CKC(dalloc(c, &c->tallies, (size_t)kSlotPhases * kPersistBlocks * kTallyN));
   if (pinned_state) {
     c->h_slots = pinned_state;

@@ -45,6 +45,11 @@ constexpr int kMaxCount = 1280;    // largest tumour count of a pair (n_tumor li
 #endif
 constexpr int kLongStream = PDFS_LONG_STREAM;
 
+// The depth-first walk's work items are drained from kSubQueues contiguous
+// ranges, each with its own cursor kCursorStride words (256 bytes) apart.
+constexpr int kSubQueues = 32;
+constexpr int kCursorStride = 32;
+
 enum PruneMode { kPruneNone = 0, kPruneEmpty = 1, kPruneBound = 2 };
 
 // Bytes per unpacked (one byte per sample) row for the MFMA pair table: the
@@ -162,6 +167,7 @@ struct Work {
   unsigned long long* seed_pairs;   // [kSeedCap]
   uint32_t* hist;                   // [kMaxCount + 1] pair-count histogram
   Item* items;
+  unsigned long long* cursors;      // [kSubQueues * kCursorStride] item cursors
   Slot* slots;
   unsigned long long* tallies;      // [kSlotPhases][kPersistBlocks][kTallyN]
   RoundState* st;

@@ -73,6 +73,7 @@ struct pdfs_ctx {
   unsigned long long* work_pairs = nullptr;   // bound mode only
   unsigned long long* seed_pairs = nullptr;
   uint32_t* hist = nullptr;
+  unsigned long long* cursors = nullptr;
   unsigned long long pair_cap = 0;
   pdfs::Item* items = nullptr;
   unsigned long long item_cap = 0;

@@ -50,7 +50,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Byte offsets of the round workspace inside the scratch array.
 struct Layout {
   size_t st, recs, slots, tallies, zero_end;   // [st, zero_end) is cleared per call
-  size_t cols, act, flags, TA, NA, A8, N8, hist, seed, pairs, work, items;
+  size_t cols, act, flags, TA, NA, A8, N8, hist, cursors, seed, pairs, work, items;
   size_t total;
   unsigned long long pair_cap = 0, item_cap = 0;
 };
@@ -81,6 +81,7 @@ bool plan(const pdfs_ctx* c, int h, Layout& L, size_t* need) {
   L.A8 = take(rows * (size_t)unpacked_row_bytes(c->w64_max));
   L.N8 = take(h == 2 ? rows * (size_t)unpacked_row_bytes(c->wn) : 0);
   L.hist = take((size_t)(kMaxCount + 1) * 4);
+  L.cursors = take((size_t)kSubQueues * kCursorStride * 8);
   L.seed = take((size_t)kSeedCap * 8);
   *need = o;
   if (o >= kScratchBytes) return false;
@@ -187,6 +188,7 @@ int32_t pdfs_best_combo_noalloc(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q,
   w.A8 = reinterpret_cast<int8_t*>(base + L.A8);
   w.N8 = reinterpret_cast<int8_t*>(base + L.N8);
   w.hist = reinterpret_cast<uint32_t*>(base + L.hist);
+  w.cursors = reinterpret_cast<unsigned long long*>(base + L.cursors);
   w.seed_pairs = reinterpret_cast<unsigned long long*>(base + L.seed);
   w.pairs = reinterpret_cast<unsigned long long*>(base + L.pairs);
   w.work_pairs = reinterpret_cast<unsigned long long*>(base + L.work);
