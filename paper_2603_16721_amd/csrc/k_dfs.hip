@@ -323,6 +323,7 @@ __device__ __forceinline__ void dfs_item(cProblem* Pp, cWork* wp, int phase, uin
 
 // kBound: bound pruning (Sec. III-E) compiled in; the other modes run the
 // instantiation without it.
+constexpr unsigned long long kMinChunk = 16;   // depth-3 candidates per work item at least
 constexpr unsigned long long kGuide = 4;   // a run: 1/kGuide of a wave's share of the rest
 constexpr unsigned long long kMaxRun = 4;   // items per cursor step at most
 
@@ -626,8 +627,13 @@ __device__ __forceinline__ void make_items_body(const Problem& P, const Work& w,
       seed ? (st->n_seed < kSeedCap ? st->n_seed : kSeedCap) : st->n_work_pairs;
   const unsigned long long nb = (np + kPairBatch - 1) / kPairBatch;
   const int amax3 = st->amax[3];
-  // chunk length so that the item list cannot overflow
+  // chunk length: shorter for a small round, so that its work still spreads
+  // over the grid (about 4 items per wave of a full grid; batches average
+  // about nA/2 candidates), and long enough that the item list cannot
+  // overflow
   unsigned long long chunk = (unsigned long long)(chunk0 > 0 ? chunk0 : w.chunk);
+  const unsigned long long spread = nb * (unsigned long long)st->nA / (8ull * kWavesPerGrid);
+  if (spread < chunk) chunk = spread < kMinChunk ? kMinChunk : spread;
   const unsigned long long room = w.item_cap > nb ? w.item_cap - nb : 1;
   const unsigned long long need = (nb * (unsigned long long)st->nA + room - 1) / room;
   if (need > chunk) chunk = need;

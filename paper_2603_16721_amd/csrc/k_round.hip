@@ -588,7 +588,6 @@ __device__ __forceinline__ void run_begin_body(const Problem& P, const Work& w, 
     st->overflow = 0;
     st->found = 0;
     st->n_tri = 0;
-    st->tri_cursor = 0;
   }
   for (int l = lane; l <= kMaxH; l += 64) {
     st->tot.visited[l] = 0;

@@ -49,7 +49,6 @@ __device__ __forceinline__ void tri_begin_body(const Work& w) {
       w.c_hist[i] = 0u;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->n_tri = 0;
-    st->tri_cursor = 0;
   }
 }
 
@@ -114,6 +113,8 @@ __device__ __forceinline__ void scan_c_body(const Work& w) {
   const int nA = st->nA;
   const int tid = threadIdx.x;
   if (tid == 0 && st->n_tri > w.tri_cap) st->overflow |= 1;
+  // the tile kernel's range cursors (the walk that used them has ended)
+  if (tid < kSubQueues) w.cursors[tid * kCursorStride] = 0ull;
   const int per = (nA + 1023) / 1024;
   const int lo = tid * per;
   const int hi = lo + per < nA ? lo + per : nA;
@@ -241,11 +242,10 @@ __device__ __forceinline__ void tile_item(const Problem& P, const Work& w, Round
 template <int W64>
 __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_dfs4_tiles(Problem P,
                                                                                         Work w) {
-  constexpr int W = 2 * W64;
   RoundState* st = w.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63;
-  const int wib = threadIdx.x >> 6;
+  const int wib = uniform(threadIdx.x >> 6);
   const unsigned long long n = st->n_tri < w.tri_cap ? st->n_tri : w.tri_cap;
   const uint32_t ntiles = (uint32_t)((n + kWave - 1) / kWave);
   const int nA = uniform(st->nA);
@@ -255,29 +255,56 @@ __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_df
   Tally tl;
   tl.init();
   unsigned long long inc = 0;
+  // Scheduling as in the depth-first walk: the tiles are split into
+  // kSubQueues contiguous ranges with their own cursors; wave g takes its
+  // first tile in range g % kSubQueues without an atomic, then grabs from
+  // that range's cursor (as many tiles as make about kGrabIters candidate
+  // rows: later tiles have shorter streams), then from the other ranges in
+  // turn.
   const uint32_t nwaves = gridDim.x * (kBlock / kWave);
-  // wave g starts with tile g; the cursor counts tiles past the first nwaves
-  uint32_t t_next = blockIdx.x * (kBlock / kWave) + wib, t_end = t_next + 1;
+  const uint32_t gw = blockIdx.x * (kBlock / kWave) + wib;
+  auto range_lo = [&](uint32_t r) {
+    return (uint32_t)((unsigned long long)ntiles * r / kSubQueues);
+  };
+  auto range_waves = [&](uint32_t r) { return (nwaves + kSubQueues - 1 - r) / kSubQueues; };
+  uint32_t qs = gw % kSubQueues;
+  uint32_t q_left = kSubQueues;
+  uint32_t t_next = range_lo(qs) + gw / kSubQueues;
+  uint32_t t_end = t_next + 1;
+  if (t_end > range_lo(qs + 1)) t_end = t_next;
   for (;;) {
     if (t_next >= t_end) {
-      uint32_t start = ntiles, cnt = 1;
-      if (lane == 0) {
-        const unsigned long long cur =
-            __hip_atomic_load(&st->tri_cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur + nwaves < ntiles) {
-          // stream length of the tile at the cursor: later tiles are shorter
-          const int cp = (int)((w.tri_s[(cur + nwaves) * kWave] >> 32) & 0xffff);
-          const int len = nA - 1 - cp;
-          cnt = len > 0 ? kGrabIters / len : kMaxGrab;
-          cnt = cnt < 1 ? 1 : (cnt > kMaxGrab ? kMaxGrab : cnt);
-          start = (uint32_t)(nwaves + atomicAdd(&st->tri_cursor, (unsigned long long)cnt));
+      uint32_t start = 0, cnt = 0;
+      while (q_left > 0) {
+        const uint32_t hi = range_lo(qs + 1);
+        const uint32_t base = range_lo(qs) + range_waves(qs);
+        if (lane == 0) {
+          unsigned long long* cur_p = w.cursors + (size_t)qs * kCursorStride;
+          const unsigned long long cur =
+              __hip_atomic_load(cur_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (base + cur < hi) {
+            // stream length of the tile at the cursor: later tiles are shorter
+            const int cp = (int)((w.tri_s[(base + cur) * kWave] >> 32) & 0xffff);
+            const int len = nA - 1 - cp;
+            int k = len > 0 ? kGrabIters / len : kMaxGrab;
+            cnt = k < 1 ? 1u : (k > kMaxGrab ? (uint32_t)kMaxGrab : (uint32_t)k);
+            start = (uint32_t)(base + atomicAdd(cur_p, (unsigned long long)cnt));
+          }
         }
+        start = (uint32_t)uniform((int)start);
+        cnt = (uint32_t)uniform((int)cnt);
+        if (cnt > 0 && start < hi) {
+          if (start + cnt > hi) cnt = hi - start;
+          break;
+        }
+        cnt = 0;
+        qs = qs + 1 == kSubQueues ? 0 : qs + 1;
+        --q_left;
       }
-      t_next = (uint32_t)uniform((int)start);
-      t_end = t_next + (uint32_t)uniform((int)cnt);
-      if (t_end > ntiles) t_end = ntiles;
+      if (cnt == 0) break;
+      t_next = start;
+      t_end = start + cnt;
     }
-    if (t_next >= ntiles) break;
     const uint32_t it = t_next++;
     tile_item<W64>(P, w, st, it, n, nA, best, tl, inc, lane);
   }

@@ -93,7 +93,6 @@ struct RoundState {
   unsigned long long tx_vis_words3, tx_vis_words4;   // visits x ceil(|U|/64)
   // ---- two-phase depth-4 (h = 4, empty-prefix pruning)
   unsigned long long n_tri;        // non-empty depth-3 prefixes listed this round
-  unsigned long long tri_cursor;   // tile cursor of the depth-4 kernel
   // ---- batched launches: best-leaf log entries per slot phase this round
   uint32_t nlog[4];
 };
