@@ -126,6 +126,43 @@ __device__ __forceinline__ int leaf_fp(const uint32_t (&z)[kMaxWN32], cu32* row,
   return c;
 }
 
+// Rows of at least this many 64-bit words keep the normal prefixes in LDS.
+#ifndef PDFS_ZLDS_MIN_W64
+#define PDFS_ZLDS_MIN_W64 10
+#endif
+constexpr int kZLdsMinW64 = PDFS_ZLDS_MIN_W64;
+
+// A lane's normal-sample prefix (its genes' normal rows joined, kMaxWN32
+// words): in registers, or -- for the widest tumour rows, whose depth-first
+// kernels are bound by registers -- in the wave's LDS slice, stored
+// [word][lane] so that a word of all 64 lanes is one conflict-free access.
+template <bool kLds>
+struct NrmPre;
+
+template <>
+struct NrmPre<false> {
+  uint32_t z[kMaxWN32];
+  __device__ uint32_t get(int k, int /*lane*/) const { return z[k]; }
+  __device__ void set(int k, int /*lane*/, uint32_t v) { z[k] = v; }
+};
+
+template <>
+struct NrmPre<true> {
+  uint32_t* s;   // [kMaxWN32][kWave] words of the wave's LDS slice
+  __device__ uint32_t get(int k, int lane) const { return s[k * kWave + lane]; }
+  __device__ void set(int k, int lane, uint32_t v) { s[k * kWave + lane] = v; }
+};
+
+// FP of a leaf from its prefix's normals z (lane `lane`) and the last gene's
+// normal row.
+template <bool kLds>
+__device__ __forceinline__ int leaf_fp_z(const NrmPre<kLds>& z, int lane, cu32* row, bool literal) {
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxWN32; ++k) c += __popc(nrm_join(z.get(k, lane), row[k], literal));
+  return c;
+}
+
 // sum over k of popcount(y[k] & r[k]) for a row already in (scalar) registers
 template <int W>
 __device__ __forceinline__ int popc_and_r(const uint32_t (&y)[W], const uint32_t (&r)[W]) {
@@ -268,12 +305,13 @@ __device__ __forceinline__ int min_tp_for(const Problem& P, int s, bool tie_wins
 // those whose TP reaches the lane's threshold (min_tp_for of the lane's best)
 // are scored and offered, which leaves the answer unchanged: a leaf below it
 // cannot replace the leaf the lane already holds.
-template <int W, bool kBound = false>
+template <int W, bool kBound, bool kZL>
 __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundState* st,
-                                        const uint32_t (&y3)[W],
-                                        const uint32_t (&z3)[kMaxWN32], uint32_t znz,
-                                        bool valid, int a3, int b3, int c, int c_first,
-                                        Best& best, Tally& tl, unsigned long long& inc) {
+                                        uint32_t (&y3)[W], const NrmPre<kZL>& z3,
+                                        uint32_t znz, bool valid, int a3, int b3, int c,
+                                        int c_first, Best& best, Tally& tl,
+                                        unsigned long long& inc) {
+  const int lane = threadIdx.x & 63;
   const int nA = uniform(st->nA);
   cu32* TA = (cu32*)w.TA;
   cu32* NA = (cu32*)w.NA;
@@ -293,9 +331,9 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
   const bool zlive = live && (znz != 0 || P.tn_literal);
   if (live) tl.xv4 += (unsigned long long)(nA - 1 - c);
   // a dead lane's TP is 0 at every d: it never counts nor offers
-  uint32_t y[W];
+  uint32_t (&y)[W] = y3;
 #pragma unroll
-  for (int k = 0; k < W; ++k) y[k] = live ? y3[k] : 0u;
+  for (int k = 0; k < W; ++k) y[k] = live ? y[k] : 0u;
   const int cmax = wave_max(live ? c : -1);   // d > cmax: no lane masks d
   // the prefix's leaves all have a smaller tuple than the best exactly when
   // (a3, b3, c) precedes the best's first three indices
@@ -305,11 +343,11 @@ __device__ __forceinline__ void expand4(const Problem& P, const Work& w, RoundSt
   uint32_t ne = 0;   // non-empty leaves of this pass (< 64 * nA)
   // leaves of candidate d in lanes m (TP >= thr): score and offer
   auto offer = [&](int d, int tp, unsigned long long m) {
-    const bool hit = (m >> (threadIdx.x & 63)) & 1ull;
+    const bool hit = __builtin_amdgcn_inverse_ballot_w64(m);
     int fp = 0;
     if (__any(hit && zlive)) {
       if (hit && zlive) {
-        fp = leaf_fp(z3, NA + (size_t)d * kMaxWN32, P.tn_literal);
+        fp = leaf_fp_z(z3, lane, NA + (size_t)d * kMaxWN32, P.tn_literal);
         tl.xfp++;
       }
     }

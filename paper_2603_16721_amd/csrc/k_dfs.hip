@@ -39,11 +39,11 @@ namespace {
 
 // Depth-4 pass over n <= 64 staged prefixes (queue entries lane | c << 6,
 // ascending c): prefix s's y2 and z2 come from lane s by cross-lane reads.
-template <int W, bool kBound>
+template <int W, bool kBound, bool kZL>
 __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundState* st,
                                        const uint32_t* q, int n, const uint32_t (&y2)[W],
-                                       const uint32_t (&z2)[kMaxWN32], int a, int b, Best& best,
-                                       Tally& tl, unsigned long long& inc, int lane) {
+                                       const NrmPre<kZL>& z2, uint32_t* zl3, int a, int b,
+                                       Best& best, Tally& tl, unsigned long long& inc, int lane) {
   const bool valid = lane < n;
   const uint32_t e = q[valid ? lane : 0];
   const int s = e & 63;
@@ -51,7 +51,8 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
   cu32* TA = (cu32*)w.TA;
   cu32* NA = (cu32*)w.NA;
   uint32_t y3[W];
-  uint32_t z3[kMaxWN32];
+  NrmPre<kZL> z3;
+  if constexpr (kZL) z3.s = zl3;
   const uint32_t vmask = valid ? ~0u : 0u;
   const int cc = valid ? c : 0;   // any in-range row for idle lanes
 #pragma unroll
@@ -62,16 +63,19 @@ __device__ __forceinline__ void depth4(const Problem& P, const Work& w, RoundSta
   uint32_t znz = 0;
 #pragma unroll
   for (int k = 0; k < kMaxWN32; ++k) {
-    uint32_t v = __shfl(z2[k], s, 64);
-    z3[k] = nrm_join(v, NA[(size_t)cc * kMaxWN32 + k], P.tn_literal) & vmask;
-    znz |= z3[k];
+    uint32_t v;
+    if constexpr (kZL) v = z2.get(k, s);   // lane s's word, from the LDS slice
+    else v = __shfl(z2.z[k], s, 64);
+    const uint32_t z = nrm_join(v, NA[(size_t)cc * kMaxWN32 + k], P.tn_literal) & vmask;
+    z3.set(k, lane, z);
+    znz |= z;
   }
   const int a3 = __shfl(a, s, 64);
   const int b3 = __shfl(b, s, 64);
   // visited at depth 4 below the prefix: sorted indices in (idx(c), G-1]
   if (valid) tl.vis4 += (unsigned long long)(P.G - 1 - w.act[c]);
   const int c_first = uniform((int)(q[0] >> 6));
-  expand4<W, kBound>(P, w, st, y3, z3, znz, valid, a3, b3, c, c_first, best, tl, inc);
+  expand4<W, kBound, kZL>(P, w, st, y3, z3, znz, valid, a3, b3, c, c_first, best, tl, inc);
 }
 
 // The per-round values the depth-first walk of one instance reads.
@@ -114,9 +118,10 @@ template <int H, int W64, bool kBound>
 __device__ __forceinline__ void dfs_item(cProblem* Pp, cWork* wp, int phase, uint32_t batch,
                                          int c_lo, int c_hi, uint32_t first_chunk,
                                          uint32_t* q, unsigned long long* sq, int& sn,
-                                         Best& best, Tally& tl, unsigned long long& inc,
-                                         int lane) {
+                                         uint32_t* zl, Best& best, Tally& tl,
+                                         unsigned long long& inc, int lane) {
   constexpr int W = 2 * W64;
+  constexpr bool kZL = W64 >= kZLdsMinW64;
   constexpr bool kPipe = W <= 16;
   constexpr int KG = W <= 8 ? 16 / W : 1;
   const Problem P = load_const(fresh(Pp));
@@ -150,19 +155,22 @@ __device__ __forceinline__ void dfs_item(cProblem* Pp, cWork* wp, int phase, uin
   }
   if (!__any(valid)) return;
   uint32_t y2[W];
-  uint32_t z2[kMaxWN32];
+  NrmPre<kZL> z2;
+  if constexpr (kZL) z2.s = zl;
   const uint32_t vmask = valid ? ~0u : 0u;
   const int ra = valid ? a : 0, rb = valid ? b : 0;   // in-range rows for idle lanes
 #pragma unroll
   for (int k = 0; k < W; ++k)
     y2[k] = TA[(size_t)ra * W + k] & TA[(size_t)rb * W + k] & vmask;
-#pragma unroll
-  for (int k = 0; k < kMaxWN32; ++k)
-    z2[k] = nrm_join(NA[(size_t)ra * kMaxWN32 + k], NA[(size_t)rb * kMaxWN32 + k],
-                     P.tn_literal) & vmask;
   uint32_t znz = 0;
 #pragma unroll
-  for (int k = 0; k < kMaxWN32; ++k) znz |= z2[k];
+  for (int k = 0; k < kMaxWN32; ++k) {
+    const uint32_t z = nrm_join(NA[(size_t)ra * kMaxWN32 + k], NA[(size_t)rb * kMaxWN32 + k],
+                                P.tn_literal) & vmask;
+    z2.set(k, lane, z);
+    znz |= z;
+  }
+  if constexpr (kZL) wave_lds_sync();   // the depth-4 passes read other lanes' words
   if (valid) {
     const int lo = c_lo > b + 1 ? c_lo : b + 1;
     if (c_hi > lo) tl.xv3 += (unsigned long long)(c_hi - lo);
@@ -189,7 +197,7 @@ __device__ __forceinline__ void dfs_item(cProblem* Pp, cWork* wp, int phase, uin
       const bool zn = znz != 0 || P.tn_literal;
       if (__any(hit && zn)) {
         if (hit && zn) {
-          fp = leaf_fp(z2, NA + (size_t)c * kMaxWN32, P.tn_literal);
+          fp = leaf_fp_z(z2, lane, NA + (size_t)c * kMaxWN32, P.tn_literal);
           tl.xfp++;
         }
       }
@@ -242,7 +250,8 @@ __device__ __forceinline__ void dfs_item(cProblem* Pp, cWork* wp, int phase, uin
     }
     int off = 0;
     while (qn - off >= kWave) {
-      depth4<W, kBound>(P2, w2, w2.st, q + off, kWave, y2, z2, a, b, best, tl, inc, lane);
+      depth4<W, kBound, kZL>(P2, w2, w2.st, q + off, kWave, y2, z2, zl + kMaxWN32 * kWave, a,
+                             b, best, tl, inc, lane);
       off += kWave;
     }
     if (off > 0) {
@@ -315,7 +324,8 @@ __device__ __forceinline__ void dfs_item(cProblem* Pp, cWork* wp, int phase, uin
   if (H == 4 && qn > 0) {
     const Problem P2 = load_const(fresh(Pp));
     const Work w2 = load_const(fresh(wp));
-    depth4<W, kBound>(P2, w2, w2.st, q, qn, y2, z2, a, b, best, tl, inc, lane);
+    depth4<W, kBound, kZL>(P2, w2, w2.st, q, qn, y2, z2, zl + kMaxWN32 * kWave, a, b, best,
+                           tl, inc, lane);
     qn = 0;
   }
   tl.ne3 += ne3;
@@ -336,7 +346,7 @@ struct DfsArgs {
 };
 
 template <int H, int W64, bool kBound>
-__global__ __launch_bounds__(256, (W64 <= 6 || (W64 <= 8 && !kBound) ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
+__global__ __launch_bounds__(256, (W64 <= 5 || (W64 <= 16 && !kBound) ? 3 : 2)) void k_dfs(Problem P, Work w, int phase) {
   constexpr int W = 2 * W64;
   // Rows of up to 8 words: candidate rows arrive in groups of KG (one
   // 16-dword scalar load for up to 4 words, one row above that), the next
@@ -348,6 +358,9 @@ __global__ __launch_bounds__(256, (W64 <= 6 || (W64 <= 8 && !kBound) ? 3 : 2)) v
   __shared__ uint32_t qbuf[kBlock / kWave][kWave * (KG + 1)];
   // h = 4, two-phase: staged long-stream prefixes before a global append
   __shared__ unsigned long long sbuf[kBlock / kWave][H == 4 ? kStage + KG * kWave : 1];
+  // the widest rows: the pairs' and the pass's normal prefixes
+  constexpr bool kZL = W64 >= kZLdsMinW64;
+  __shared__ uint32_t zbuf[kBlock / kWave][kZL ? 2 * kMaxWN32 * kWave : 1];
   RoundState* st = w.st;
   if (st->done) return;
   const auto* args = (const __attribute__((address_space(4))) DfsArgs*)
@@ -440,8 +453,8 @@ __global__ __launch_bounds__(256, (W64 <= 6 || (W64 <= 8 && !kBound) ? 3 : 2)) v
     const int c_hi = uniform((int)items[t_last].c_hi);
     const uint32_t first_chunk = (uint32_t)uniform((int)items[t_next].pad) & 1u;
     t_next = t_last + 1;
-    dfs_item<H, W64, kBound>(Pp, wp, phase, batch, c_lo, c_hi, first_chunk, q, sq, sn, best,
-                             tl, inc, lane);
+    dfs_item<H, W64, kBound>(Pp, wp, phase, batch, c_lo, c_hi, first_chunk, q, sq, sn,
+                             zbuf[wib], best, tl, inc, lane);
   }
   if (H == 4 && sn > 0) append_staged(load_const(fresh(wp)), st, sq, sn, lane);
 
@@ -482,12 +495,14 @@ __global__ __launch_bounds__(256, (W64 <= 6 || (W64 <= 8 && !kBound) ? 3 : 2)) v
 // that instance its staged prefixes, best leaf and counts, and never returns
 // to it within the launch.
 template <int H, int W64, bool kBound>
-__global__ __launch_bounds__(256, (W64 <= 6 ? 3 : 2)) void k_dfs_multi(
+__global__ __launch_bounds__(256, (W64 <= 6 || (W64 <= 16 && !kBound) ? 3 : 2)) void k_dfs_multi(
     const BatchDesc* __restrict__ bd, BatchQueue* __restrict__ bq, int phase) {
   constexpr int W = 2 * W64;
   constexpr int KG = W <= 8 ? 16 / W : 1;
   __shared__ uint32_t qbuf[kBlock / kWave][kWave * (KG + 1)];
   __shared__ unsigned long long sbuf[kBlock / kWave][H == 4 ? kStage + KG * kWave : 1];
+  constexpr bool kZL = W64 >= kZLdsMinW64;
+  __shared__ uint32_t zbuf[kBlock / kWave][kZL ? 2 * kMaxWN32 * kWave : 1];
   const int lane = threadIdx.x & 63;
   const int wib = uniform(threadIdx.x >> 6);
   uint32_t* q = qbuf[wib];
@@ -563,8 +578,8 @@ __global__ __launch_bounds__(256, (W64 <= 6 ? 3 : 2)) void k_dfs_multi(
       const uint32_t it = g - lo;
       dfs_item<H, W64, kBound>(Pp, wp, phase, (uint32_t)uniform((int)items[it].batch),
                                uniform((int)items[it].c_lo), uniform((int)items[it].c_hi),
-                               (uint32_t)uniform((int)items[it].pad) & 1u, q, sq, sn, best, tl,
-                               inc, lane);
+                               (uint32_t)uniform((int)items[it].pad) & 1u, q, sq, sn, zbuf[wib],
+                               best, tl, inc, lane);
     }
   }
   if (cur >= 0) flush();

@@ -200,9 +200,11 @@ constexpr int kMaxGrab = 16;
 // listed in all), one per lane.
 template <int W64>
 __device__ __forceinline__ void tile_item(const Problem& P, const Work& w, RoundState* st,
-                                          uint32_t it, unsigned long long n, int nA, Best& best,
-                                          Tally& tl, unsigned long long& inc, int lane) {
+                                          uint32_t it, unsigned long long n, int nA, uint32_t* zl,
+                                          Best& best, Tally& tl, unsigned long long& inc,
+                                          int lane) {
   constexpr int W = 2 * W64;
+  constexpr bool kZL = W64 >= kZLdsMinW64;
   cu32* TA = (cu32*)w.TA;
   cu32* NA = (cu32*)w.NA;
   const unsigned long long t0 = (unsigned long long)it * kWave;
@@ -220,28 +222,33 @@ __device__ __forceinline__ void tile_item(const Problem& P, const Work& w, Round
   if (!valid) a3 = b3 = c = 0;
   const uint32_t vmask = valid ? ~0u : 0u;
   uint32_t y3[W];
-  uint32_t z3[kMaxWN32];
+  NrmPre<kZL> z3;
+  if constexpr (kZL) z3.s = zl;
 #pragma unroll
   for (int k = 0; k < W; ++k)
     y3[k] = TA[(size_t)a3 * W + k] & TA[(size_t)b3 * W + k] & TA[(size_t)c * W + k] & vmask;
   uint32_t znz = 0;
 #pragma unroll
   for (int k = 0; k < kMaxWN32; ++k) {
-    z3[k] = nrm_join(nrm_join(NA[(size_t)a3 * kMaxWN32 + k], NA[(size_t)b3 * kMaxWN32 + k],
-                              P.tn_literal),
-                     NA[(size_t)c * kMaxWN32 + k], P.tn_literal) & vmask;
-    znz |= z3[k];
+    const uint32_t z =
+        nrm_join(nrm_join(NA[(size_t)a3 * kMaxWN32 + k], NA[(size_t)b3 * kMaxWN32 + k],
+                          P.tn_literal),
+                 NA[(size_t)c * kMaxWN32 + k], P.tn_literal) & vmask;
+    z3.set(k, lane, z);
+    znz |= z;
   }
   // visited at depth 4 below the prefix: sorted indices in (idx(c), G-1]
   if (valid) tl.vis4 += (unsigned long long)(P.G - 1 - w.act[c]);
   int cmin = valid ? c : 0x7fffffff;
   for (int o = 32; o > 0; o >>= 1) cmin = min(cmin, __shfl_xor(cmin, o, 64));
-  expand4<W>(P, w, st, y3, z3, znz, valid, a3, b3, c, uniform(cmin), best, tl, inc);
+  expand4<W, false, kZL>(P, w, st, y3, z3, znz, valid, a3, b3, c, uniform(cmin), best, tl, inc);
 }
 
 template <int W64>
 __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_dfs4_tiles(Problem P,
                                                                                         Work w) {
+  constexpr bool kZL = W64 >= kZLdsMinW64;
+  __shared__ uint32_t zbuf[kBlock / kWave][kZL ? kMaxWN32 * kWave : 1];
   RoundState* st = w.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63;
@@ -306,7 +313,7 @@ __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_df
       t_end = start + cnt;
     }
     const uint32_t it = t_next++;
-    tile_item<W64>(P, w, st, it, n, nA, best, tl, inc, lane);
+    tile_item<W64>(P, w, st, it, n, nA, zbuf[wib], best, tl, inc, lane);
   }
 
   Slot sl = empty_slot();
@@ -333,8 +340,10 @@ __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_df
 template <int W64>
 __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_dfs4_tiles_multi(
     const BatchDesc* __restrict__ bd, BatchQueue* __restrict__ bq) {
+  constexpr bool kZL = W64 >= kZLdsMinW64;
+  __shared__ uint32_t zbuf[kBlock / kWave][kZL ? kMaxWN32 * kWave : 1];
   const int lane = threadIdx.x & 63;
-  const int wib = threadIdx.x >> 6;
+  const int wib = uniform(threadIdx.x >> 6);
   const uint32_t total = (uint32_t)uniform((int)bq->total);
   int cur = -1;
   uint32_t lo = 0, hi = 0;
@@ -394,7 +403,7 @@ __global__ __launch_bounds__(256, (W64 <= PDFS_TILE3_MAX_W64 ? 3 : 2)) void k_df
       tl.init();
       inc = 0;
     }
-    tile_item<W64>(P, w, st, g - lo, n, nA, best, tl, inc, lane);
+    tile_item<W64>(P, w, st, g - lo, n, nA, zbuf[wib], best, tl, inc, lane);
   }
   if (cur >= 0) flush();
 }
