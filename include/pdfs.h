@@ -109,7 +109,13 @@ typedef struct {
     int32_t device;     /* HIP device ordinal                            */
     void *stream;       /* hipStream_t on that device, or NULL           */
     int32_t flags;      /* PDFS_OPT_* bits                               */
-    int32_t reserved;
+    int32_t pair_cap;   /* initial capacity of the round's pair list
+                           (pairs); <= 0: the default, max(2^21, 128 x
+                           the active genes of the first round), at most
+                           every pair.  A round that emits more pairs
+                           grows the list to its count + 1/4 and is run
+                           again, so this only trades memory for an
+                           occasional repeated round. */
 } pdfs_options;
 
 /* One chosen combination (one greedy round). */

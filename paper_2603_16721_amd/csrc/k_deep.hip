@@ -31,6 +31,8 @@
 // loop bounds (sorted indices in (idx(g_l), G-h+l]), per wave in LDS, then
 // one atomic per wave and depth.  The depth-2 and depth-3 visit counts come
 // from the pair kernel, as for h <= 4.
+#include <algorithm>
+
 #include "dfs_core.h"
 #include "pdfs_dev.h"
 #include "slot_reduce.h"
@@ -507,7 +509,31 @@ hipError_t launch_deep_w(const Problem& P, const Work& w, int phase, hipStream_t
                                : launch_deep_b<W64, false>(P, w, phase, s);
 }
 
+// 32-bit words of the rings and frames a launch at row width w64 uses: one
+// area per wave of its grid (resident blocks x compute units, at most
+// kPersistBlocks blocks), the larger of the two instantiations.
+template <int W64>
+size_t deep_words_w(int n_cu) {
+  static const int per_cu = std::max(resident_deep(&k_dfs_deep<W64, false>),
+                                     resident_deep(&k_dfs_deep<W64, true>));
+  size_t g = (size_t)per_cu * (size_t)(n_cu > 0 ? n_cu : 1);
+  if (g > (size_t)kPersistBlocks) g = kPersistBlocks;
+  const size_t W = 2 * (size_t)W64;
+  return g * (kBlock / kWave) * (size_t)(kMaxH - 3) * ((W + kMaxH) * kDeepQ + (W + kMaxH + 1) * kWave);
+}
+
 }  // namespace
+
+size_t deep_ring_words(int w64_max, int n_cu) {
+  size_t m = 0;
+#define PDFS_CASE(n) \
+  if (n <= w64_max) m = std::max(m, deep_words_w<n>(n_cu));
+  PDFS_CASE(1) PDFS_CASE(2) PDFS_CASE(3) PDFS_CASE(4) PDFS_CASE(5) PDFS_CASE(6)
+  PDFS_CASE(7) PDFS_CASE(8) PDFS_CASE(10) PDFS_CASE(12) PDFS_CASE(14) PDFS_CASE(16)
+  PDFS_CASE(18) PDFS_CASE(20)
+#undef PDFS_CASE
+  return m;
+}
 
 hipError_t launch_dfs_deep(const Problem& P, const Work& w, int phase, hipStream_t s) {
   if (!w.deepq || P.h < 5 || P.h > kMaxH || phase < 1 || phase > 2 ||

@@ -704,7 +704,7 @@ __global__ __launch_bounds__(256) void k_make_items_m(const BatchDesc* __restric
 __device__ __forceinline__ void begin_bound_lists_body(const Work& w) {
   RoundState* st = w.st;
   if (st->done) return;
-  if (st->n_pairs > w.pair_cap) { st->n_pairs = w.pair_cap; st->overflow = 1; }
+  if (st->n_pairs > w.pair_cap) st->overflow |= kOverflowPairs;   // n_pairs: the count emitted
   st->n_work_pairs = 0;
   st->n_seed = 0;
   st->n_items = 0;
@@ -724,8 +724,12 @@ __device__ __forceinline__ void use_all_pairs_body(const Work& w) {
   RoundState* st = w.st;
   if (st->done) return;
   unsigned long long n = st->n_pairs;
-  if (n > w.pair_cap) { n = w.pair_cap; st->overflow = 1; }
-  st->n_pairs = n;
+  if (n > w.pair_cap) {
+    st->overflow |= kOverflowPairs;   // n_pairs keeps the count emitted
+    n = w.pair_cap;
+  } else {
+    st->n_pairs = n;
+  }
   st->n_work_pairs = n;
   st->n_items = 0;
   st->cursor = 0;

@@ -596,6 +596,15 @@ __device__ __forceinline__ void run_begin_body(const Problem& P, const Work& w, 
   }
 }
 
+// After the host grew a list the stopped round overflowed: the run goes on
+// from the same state (that round was not committed).
+__global__ void k_run_resume(Work w) {
+  if (threadIdx.x == 0) {
+    w.st->overflow = 0;
+    w.st->done = 0;
+  }
+}
+
 __global__ void k_run_begin(Problem P, Work w, int max_rounds) {
   run_begin_body(P, w, max_rounds);
 }
@@ -649,6 +658,11 @@ hipError_t launch_normal_counts(const uint64_t* Ns, int G, int wn, int32_t* ncou
 hipError_t launch_check_pad(const uint64_t* T, int64_t ts, int G, int n, int* bad,
                             hipStream_t s) {
   k_check_pad<<<(G + 255) / 256, 256, 0, s>>>(T, ts, G, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_run_resume(const Work& w, hipStream_t s) {
+  k_run_resume<<<1, 64, 0, s>>>(w);
   return hipGetLastError();
 }
 

@@ -72,15 +72,6 @@ void release(pdfs_ctx* c) {
 
 int words(int n) { return (n + 63) / 64; }
 
-// 32-bit words of the h >= 5 prefix rings and suspended-expansion frames:
-// every wave of a full persistent grid, one ring and one frame per depth
-// 3..kMaxH-1, rows of up to w64max 64-bit words
-static size_t deepq_words(int w64max) {
-  const size_t W = 2 * (size_t)w64max;
-  return (size_t)kWavesPerGrid * (kMaxH - 3) *
-         ((W + kMaxH) * kDeepQ + (W + kMaxH + 1) * kWave);
-}
-
 // Exhaustive mode makes every gene a row of the round (its row over the
 // uncovered samples may be empty), so the row-indexed buffers must hold G rows
 // instead of the first round's active count.  Drops the buffers sized by the
@@ -108,6 +99,60 @@ static int32_t grow_for_all_genes(pdfs_ctx* c) {
   return PDFS_OK;
 }
 
+// Pair-list capacity: every pair of nA rows at most; the default start is
+// max(2^21, 128 per active gene) (a G = 20000 cohort emits 1.5 M pairs in its
+// densest round), and a round that emits more grows the list (regrow_pairs).
+static unsigned long long pair_cap_for(int nA, unsigned long long hint) {
+  const unsigned long long all = (unsigned long long)nA * (nA > 0 ? nA - 1 : 0) / 2;
+  unsigned long long n = hint > 0 ? hint : 128ull * (unsigned long long)nA;
+  if (hint == 0 && n < (1ull << 21)) n = 1ull << 21;
+  if (n > all) n = all;
+  return n < 64 ? 64 : n;
+}
+
+// Item-list capacity for a pair list of n pairs (two chunks per 64-pair batch,
+// at least 2^20; the item builder lengthens chunks so that it never overflows).
+static unsigned long long item_cap_for(unsigned long long n) {
+  const unsigned long long ic = 2 * ((n + kPairBatch - 1) / kPairBatch);
+  return ic < (1ull << 20) ? 1ull << 20 : ic;
+}
+
+// (Re)allocates the pair list (and its bound-mode work copy) and the item list
+// for n pairs; the captured rounds holding the old addresses are dropped.
+static int32_t alloc_pair_lists(pdfs_ctx* c, unsigned long long n) {
+  void** bufs[] = {(void**)&c->pairs, (void**)&c->work_pairs, (void**)&c->items};
+  for (void** b : bufs) {
+    dfree(c, *b);
+    *b = nullptr;
+  }
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->pair_cap = c->item_cap = 0;
+  CK(c, dalloc(c, &c->pairs, (size_t)n));
+  if (c->prune_mode == PDFS_PRUNE_BOUND) CK(c, dalloc(c, &c->work_pairs, (size_t)n));
+  const unsigned long long ic = item_cap_for(n);
+  CK(c, dalloc(c, &c->items, (size_t)ic));
+  c->pair_cap = n;
+  c->item_cap = ic;
+  return PDFS_OK;
+}
+
+// A round emitted `emitted` pairs into a shorter list: grows the list to that
+// count + 1/4 (the caller has drained every stream that uses it).
+static int32_t regrow_pairs_now(pdfs_ctx* c, unsigned long long emitted) {
+  unsigned long long n = emitted + emitted / 4 + (1ull << 16);
+  const unsigned long long all = pair_cap_for(c->nA_max, ~0ull);
+  if (n > all) n = all;
+  if (n <= c->pair_cap) return fail(c, PDFS_ERR_DEVICE, "pair count above every pair");
+  return alloc_pair_lists(c, n);
+}
+
+// The same after the context's own stream has drained.
+static int32_t regrow_pairs(pdfs_ctx* c, unsigned long long emitted) {
+  CK(c, hipStreamSynchronize(c->stream));
+  return regrow_pairs_now(c, emitted);
+}
+
 // Allocates the pair list, item list and normal bytes when a call first needs
 // them.
 int32_t ensure_workspace(pdfs_ctx* c, int h) {
@@ -116,20 +161,14 @@ int32_t ensure_workspace(pdfs_ctx* c, int h) {
     if (rc != PDFS_OK) return rc;
   }
   if (h >= 3 && !c->pairs) {
-    unsigned long long n = (unsigned long long)c->nA_max * (c->nA_max > 0 ? c->nA_max - 1 : 0) / 2;
-    if (n < 64) n = 64;
-    c->pair_cap = n;
-    CK(c, dalloc(c, &c->pairs, (size_t)n));
-    unsigned long long ic = 2 * ((n + kPairBatch - 1) / kPairBatch);
-    if (ic < (1ull << 20)) ic = 1ull << 20;
-    c->item_cap = ic;
-    CK(c, dalloc(c, &c->items, (size_t)ic));
-    CK(c, dalloc(c, &c->seed_pairs, (size_t)kSeedCap));
+    const int32_t rc = alloc_pair_lists(c, pair_cap_for(c->nA_max, c->pair_cap_hint));
+    if (rc != PDFS_OK) return rc;
   }
+  if (h >= 3 && !c->seed_pairs) CK(c, dalloc(c, &c->seed_pairs, (size_t)kSeedCap));
   if (h >= 3 && c->prune_mode == PDFS_PRUNE_BOUND && !c->work_pairs)
     CK(c, dalloc(c, &c->work_pairs, (size_t)c->pair_cap));
   if (h >= 5 && !c->deepq)
-    CK(c, dalloc(c, &c->deepq, deepq_words(c->w64_max)));
+    CK(c, dalloc(c, &c->deepq, deep_ring_words(c->w64_max, c->n_cu)));
   if (h == 2 && !c->N8) {
     size_t rows = (size_t)((c->nA_max + 127) / 128 * 128 + 128);
     CK(c, dalloc(c, &c->N8, rows * (size_t)unpacked_row_bytes(c->wn)));
@@ -312,22 +351,27 @@ static int32_t size_triples(pdfs_ctx* c, int h, int n_unc) {
   const int w64 = dfs_row_words(words(n_unc > 0 ? n_unc : 1));
   if (w64 < 0 || w64 > c->w64_max) return PDFS_OK;   // reported when the run starts
   if (!c->c_hist) CK(c, dalloc(c, &c->c_hist, (size_t)c->nA_max + 1));
-  const Problem P = make_problem(c, 4, 1, 1);
-  Work w = make_work(c, w64, c->n_tumor + 1);
-  w.tri_cap = 0;
   hipStream_t s = c->stream;
-  CK(c, launch_run_begin(P, w, 1, s));
-  CK(c, launch_round_begin(P, w, s));
-  CK(c, launch_active(P, w, s));
-  CK(c, launch_gather_active(P, w, true, false, s));
-  CK(c, launch_pairs(P, w, s));
-  CK(c, launch_use_all_pairs(w, s));
-  CK(c, launch_make_items(P, w, false, s));
-  CK(c, launch_tri_begin(w, s));
-  CK(c, launch_count_long(P, w, s));
   RoundState* hs = &c->h_slots[c->next_slot];
-  CK(c, hipMemcpyAsync(hs, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
-  CK(c, hipStreamSynchronize(s));
+  for (int attempt = 0;; ++attempt) {
+    const Problem P = make_problem(c, 4, 1, 1);
+    Work w = make_work(c, w64, c->n_tumor + 1);
+    w.tri_cap = 0;
+    CK(c, launch_run_begin(P, w, 1, s));
+    CK(c, launch_round_begin(P, w, s));
+    CK(c, launch_active(P, w, s));
+    CK(c, launch_gather_active(P, w, true, false, s));
+    CK(c, launch_pairs(P, w, s));
+    CK(c, launch_use_all_pairs(w, s));
+    CK(c, launch_make_items(P, w, false, s));
+    CK(c, launch_tri_begin(w, s));
+    CK(c, launch_count_long(P, w, s));
+    CK(c, hipMemcpyAsync(hs, c->st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
+    CK(c, hipStreamSynchronize(s));
+    if (hs->overflow != kOverflowPairs || attempt > 0) break;
+    const int32_t rc = regrow_pairs(c, hs->n_pairs);
+    if (rc != PDFS_OK) return rc;
+  }
   if (hs->overflow) return PDFS_OK;   // the run itself reports it
   const unsigned long long need = hs->n_tri;
   if (need > c->tri_cap) {
@@ -348,6 +392,10 @@ static int32_t size_triples(pdfs_ctx* c, int h, int n_unc) {
   }
   c->two_phase = true;
   return PDFS_OK;
+}
+
+int32_t grow_pair_list(pdfs_ctx* c, unsigned long long emitted) {
+  return regrow_pairs_now(c, emitted);
 }
 
 int32_t grow_row_width(pdfs_ctx* c, int w64) {
@@ -470,9 +518,33 @@ int32_t run_poll(pdfs_ctx* c, bool wait, bool* ready, bool* done) {
     r.active = false;
     return fail(c, PDFS_ERR_DEVICE, "deep walk scheduler made no progress");
   }
+  if (st.overflow == kOverflowPairs) {
+    // The round emitted more pairs than the list holds and was not
+    // committed (nor anything after it: the run stopped there).  Grow the
+    // list, clear the flags and go on from the same uncovered set.
+    const unsigned long long emitted = st.n_pairs;
+    const int executed = st.executed;
+    int32_t rc = regrow_pairs(c, emitted);   // waits for the chunks in flight
+    if (rc != PDFS_OK) {
+      r.active = false;
+      return rc;
+    }
+    Work w0 = make_work(c, 1, r.target);
+    rc = launch_run_resume(w0, c->stream) == hipSuccess ? PDFS_OK : PDFS_ERR_DEVICE;
+    if (rc != PDFS_OK) {
+      r.active = false;
+      return fail(c, rc, "resume after regrowing the pair list");
+    }
+    r.inflight = 0;
+    r.enqueued = executed;
+    r.executed_before = executed;
+    r.chunk = 1;
+    r.t_prev = std::chrono::steady_clock::now();
+    return PDFS_OK;
+  }
   if (st.overflow) {
     r.active = false;
-    return fail(c, PDFS_ERR_OUT_OF_MEMORY, "pair or item list capacity exceeded");
+    return fail(c, PDFS_ERR_OUT_OF_MEMORY, "item or prefix list capacity exceeded");
   }
   if (st.executed > c->n_tumor + 2) {
     r.active = false;
@@ -629,14 +701,19 @@ size_t footprint_bytes(int G, int n_tumor, int n_normal, int nA_max, int h, int 
   b += (size_t)kSlotPhases * kSlotsPerPhase * sizeof(Slot);
   b += (size_t)kSlotPhases * kPersistBlocks * kTallyN * 8;
   if (h >= 3) {
-    size_t pairs = (size_t)nA_max * (nA_max > 0 ? nA_max - 1 : 0) / 2;
-    if (pairs < 64) pairs = 64;
-    size_t items = 2 * ((pairs + kPairBatch - 1) / kPairBatch);
-    if (items < ((size_t)1 << 20)) items = (size_t)1 << 20;
-    b += pairs * 8 * (prune_mode == PDFS_PRUNE_BOUND ? 2 : 1) + items * sizeof(Item);
+    const size_t pairs = (size_t)pair_cap_for(nA_max, 0);
+    const size_t items = (size_t)item_cap_for(pairs);
+    b += pairs * 8 * (prune_mode == PDFS_PRUNE_BOUND ? 2 : 1) + items * sizeof(Item) +
+         (size_t)kSeedCap * 8;
   }
   if (h == 2) b += rows * (size_t)unpacked_row_bytes((int)wn);
-  if (h >= 5) b += deepq_words(w64max) * 4;
+  if (h >= 5) {
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      n_cu = 256;
+    b += deep_ring_words(w64max, n_cu) * 4;
+  }
   return b + ((size_t)1 << 20);
 }
 
@@ -725,6 +802,7 @@ int32_t create_ctx(const pdfs_matrix* m, const pdfs_options* opt, pdfs_ctx** out
   c->async_alloc = async_alloc && c->stream != nullptr;
   c->prune_mode = mode;
   c->time_kernels = opt && (opt->flags & PDFS_OPT_TIME_KERNELS);
+  c->pair_cap_hint = opt && opt->pair_cap > 0 ? (unsigned long long)opt->pair_cap : 0ull;
   c->tn_literal = opt && (opt->flags & PDFS_OPT_TN_LITERAL);
   c->G = m->G; c->n_tumor = m->n_tumor; c->n_normal = m->n_normal;
   c->wt = wt; c->wn = wn_in > 0 ? wn_in : 1;

@@ -600,6 +600,32 @@ int32_t run_multi(pdfs_batch* b, const int32_t* h, uint32_t p, uint32_t q, const
     slot = (slot + 1) % kDepth;
     finished = true;
     int executed = 0;
+    // instances whose pair list was too small: their round stopped uncommitted;
+    // once everything queued has drained, grow their lists and go on
+    bool regrown = false;
+    for (int k = 0; k < n; ++k) {
+      if (hs[k].overflow != kOverflowPairs) continue;
+      if (!regrown) {
+        BCK(hipStreamSynchronize(b->ms));
+        regrown = true;
+      }
+      pdfs_ctx* c = b->ctx[m.order[k]];
+      rc = grow_pair_list(c, hs[k].n_pairs);
+      if (rc != PDFS_OK) return batch_fail(b, rc, m.order[k]);
+      Work w = make_work(c, 1, m.target[k]);
+      w.st = b->st_all + k;
+      BCK(launch_run_resume(w, b->ms));
+    }
+    if (regrown) {
+      // the descriptors and captured rounds hold the old list addresses; the
+      // chunk still in flight was a no-op for the regrown instances
+      for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+      b->graphs.clear();
+      for (auto& kv : b->desc_fresh) kv.second = false;
+      inflight = 0;
+      finished = false;
+      continue;
+    }
     for (int k = 0; k < n; ++k) {
       const RoundState& st = hs[k];
       if (st.overflow & 2) return batch_fail(b, PDFS_ERR_DEVICE, "instance " +

@@ -52,6 +52,9 @@ constexpr int kCursorStride = 32;
 
 enum PruneMode { kPruneNone = 0, kPruneEmpty = 1, kPruneBound = 2 };
 
+// RoundState::overflow: the pair list was too small for the round's pairs
+constexpr int32_t kOverflowPairs = 1 | 8;
+
 // Bytes per unpacked (one byte per sample) row for the MFMA pair table: the
 // row's 64-bit words times 64, rounded up to the kernel's 128-byte K chunk.
 __host__ __device__ constexpr int unpacked_row_bytes(int w64) { return 128 * ((w64 + 1) / 2); }
@@ -81,7 +84,9 @@ struct RoundState {
   unsigned long long n_seed;       // pairs selected for the seed phase
   int32_t seed_t;                  // seed threshold on the pair count
   int32_t overflow;                // bit 0: a list hit its capacity; bit 1: corrupt slot;
-                                   // bit 2: the h >= 5 walk's scheduler stalled
+                                   // bit 2: the h >= 5 walk's scheduler stalled; bit 3
+                                   // (with bit 0): it was the pair list, and n_pairs
+                                   // holds the count the round emitted
   Counters cnt;                    // this round's counters
   // work the DFS kernels had to do (active candidates only)
   unsigned long long x_vis3, x_vis4, x_leaves, x_fp_leaves;
@@ -264,6 +269,10 @@ hipError_t launch_clear_slots(Slot* slots, int n, hipStream_t s);
 hipError_t launch_zero_u32(void* p, size_t n32, hipStream_t s);
 hipError_t launch_fill_u(uint64_t* U, int wt, int n, hipStream_t s);
 hipError_t launch_run_begin(const Problem& P, const Work& w, int max_rounds, hipStream_t s);
+hipError_t launch_run_resume(const Work& w, hipStream_t s);
+// 32-bit words of the h >= 5 walk's rings and frames for rows of up to
+// w64_max words on a device of n_cu compute units (the launched grids' size).
+size_t deep_ring_words(int w64_max, int n_cu);
 
 // batched launches over n instances (descriptors bd in device memory; every
 // instance at the same row width, h in {3, 4}); the depth-first steps take a

@@ -75,6 +75,7 @@ struct pdfs_ctx {
   uint32_t* hist = nullptr;
   unsigned long long* cursors = nullptr;
   unsigned long long pair_cap = 0;
+  unsigned long long pair_cap_hint = 0;   // pdfs_options::pair_cap (0: default)
   pdfs::Item* items = nullptr;
   unsigned long long item_cap = 0;
   // two-phase depth-4 (h = 4, empty-prefix pruning): triple lists and per-c
@@ -133,6 +134,9 @@ void end_stats(pdfs_ctx* c, pdfs_stats* st, std::chrono::steady_clock::time_poin
 const std::string& create_error();
 // Row-indexed buffers (re-packed rows, unpacked bytes) regrown to hold rows of
 // w64 words (batched launches run every instance at the widest width).
+// Grows the pair list (and the item list) after a round emitted `emitted`
+// pairs into it; the caller has drained every stream that uses the context.
+int32_t grow_pair_list(pdfs_ctx* c, unsigned long long emitted);
 int32_t grow_row_width(pdfs_ctx* c, int w64);
 // Workspace of a run of depth h from |U| = n_unc: lists allocated, and for
 // the two-phase path the prefix lists sized by a counting pass.

@@ -44,7 +44,7 @@ PDFS_OPT_TIME_KERNELS = 1
 class pdfs_options(ctypes.Structure):
     _fields_ = [("prune_mode", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("pair_cap", ctypes.c_int32)]
 
 
 class pdfs_combo(ctypes.Structure):
@@ -181,11 +181,12 @@ def _matrix_arg(tumor, normal, n_tumor, n_normal):
 
 
 def pdfs_create(tumor, normal, n_tumor, n_normal, prune_mode="bound", device=0, stream=None,
-                flags=0):
+                flags=0, pair_cap=0):
     """Returns an opaque context handle (int).  Raises PdfsError on failure."""
     m, keep = _matrix_arg(tumor, normal, n_tumor, n_normal)
     mode = PRUNE_MODES[prune_mode] if isinstance(prune_mode, str) else int(prune_mode)
-    opt = pdfs_options(prune_mode=mode, device=device, stream=stream, flags=flags)
+    opt = pdfs_options(prune_mode=mode, device=device, stream=stream, flags=flags,
+                       pair_cap=pair_cap)
     out = ctypes.c_void_p()
     rc = lib.pdfs_create(ctypes.byref(m), ctypes.byref(opt), ctypes.byref(out))
     del keep
@@ -281,13 +282,14 @@ class Solver:
     """Owns one context for a cohort (packed uint64 rows, LSB-first samples)."""
 
     def __init__(self, tumor, normal, n_tumor, n_normal, prune_mode="bound", device=0,
-                 stream=None, time_kernels=False, tn_literal=False):
+                 stream=None, time_kernels=False, tn_literal=False, pair_cap=0):
         self.n_tumor = n_tumor
         self.n_normal = n_normal
         self.ctx = None
         flags = (PDFS_OPT_TIME_KERNELS if time_kernels else 0) | \
             (PDFS_OPT_TN_LITERAL if tn_literal else 0)
-        self.ctx = pdfs_create(tumor, normal, n_tumor, n_normal, prune_mode, device, stream, flags)
+        self.ctx = pdfs_create(tumor, normal, n_tumor, n_normal, prune_mode, device, stream, flags,
+                               pair_cap)
 
     def close(self):
         if self.ctx:
@@ -321,10 +323,11 @@ class Solver:
 
 
 def pdfs_batch_create(instances, prune_mode="bound", device=0, autotune=False,
-                      streams_only=False):
+                      streams_only=False, pair_cap=0):
     """instances: list of (tumor, normal, n_tumor, n_normal) host arrays.  Returns a handle.
     streams_only: each instance's own launches on the batch's streams instead of one
-    launch per round step over all instances."""
+    launch per round step over all instances.  pair_cap: every instance's initial
+    pair-list capacity (pdfs_options.pair_cap)."""
     mats, keep = [], []
     for (T, N, nt, nn) in instances:
         m, k = _matrix_arg(T, N, nt, nn)
@@ -334,7 +337,7 @@ def pdfs_batch_create(instances, prune_mode="bound", device=0, autotune=False,
     mode = PRUNE_MODES[prune_mode] if isinstance(prune_mode, str) else int(prune_mode)
     opt = pdfs_options(prune_mode=mode, device=device, stream=None,
                        flags=(PDFS_OPT_AUTOTUNE if autotune else 0) |
-                       (PDFS_OPT_BATCH_STREAMS if streams_only else 0))
+                       (PDFS_OPT_BATCH_STREAMS if streams_only else 0), pair_cap=pair_cap)
     out = ctypes.c_void_p()
     rc = lib.pdfs_batch_create(arr, len(mats), ctypes.byref(opt), ctypes.byref(out))
     del keep

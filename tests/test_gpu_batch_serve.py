@@ -31,11 +31,11 @@ def _compact(rounds):
     return [[*r["genes"], r["tp"], r["fp"], r["score_num"]] for r in rounds]
 
 
-def _batch(pdfs, idx, autotune=False, mode="bound", streams_only=False):
+def _batch(pdfs, idx, autotune=False, mode="bound", streams_only=False, pair_cap=0):
     insts = [synth.batched_instance(i) for i in idx]
     packed = [(I.packed(), I) for I in insts]
     b = pdfs.pdfs_batch_create([(T, N, I.n_tumor, I.n_normal) for (T, N), I in packed], mode,
-                               autotune=autotune, streams_only=streams_only)
+                               autotune=autotune, streams_only=streams_only, pair_cap=pair_cap)
     return b, insts
 
 
@@ -84,6 +84,25 @@ def test_batched_streams_path_matches_oracle(pdfs, mode):
     gold = _golden("batched")
     idx = [2, 5, 12, 20]
     b, insts = _batch(pdfs, idx, mode=mode, streams_only=True)
+    try:
+        res, _ = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
+                                     n_tumors=[I.n_tumor for I in insts])
+    finally:
+        pdfs.pdfs_batch_destroy(b)
+    for k, i in enumerate(idx):
+        assert _compact(res[k]) == gold[str(i)]["rounds"], (mode, i)
+
+
+@pytest.mark.parametrize("streams_only", [False, True])
+@pytest.mark.parametrize("mode", ["bound", "empty"])
+def test_batched_pair_list_regrowth(pdfs, mode, streams_only):
+    """Every instance starts with a 64-pair list: the rounds that emit more
+    grow their instance's list and run again (one launch per round step over
+    all instances, or each instance on the batch's streams); the results are
+    the oracle's."""
+    gold = _golden("batched")
+    idx = [0, 3, 5, 12, 16, 21]
+    b, insts = _batch(pdfs, idx, mode=mode, streams_only=streams_only, pair_cap=64)
     try:
         res, _ = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
                                      n_tumors=[I.n_tumor for I in insts])

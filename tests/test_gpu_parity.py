@@ -311,6 +311,50 @@ def test_two_phase_depth4_medium(pdfs):
         pdfs.pdfs_destroy(ctx)
 
 
+@pytest.mark.parametrize("mode", ["empty", "bound"])
+def test_pair_list_regrowth(pdfs, mode):
+    """A pair list far too small for the cohort (64 pairs): each round that
+    emits more pairs grows it and runs again from the same uncovered set, so
+    the whole cover -- and in empty mode every counter -- equals the
+    oracle's.  The grown list serves a second run on the same context, and a
+    run whose starting mask already meets the target returns no round."""
+    I = synth.workload_h3_g5000()
+    T, N = I.packed()
+    g = _golden("h3_G5000_empty_all_rounds")
+    with pdfs.Solver(T, N, I.n_tumor, I.n_normal, mode, pair_cap=64) as s:
+        for _ in range(2):
+            got, stats, final = s.wsc(3, 1, 10, target=I.target_covered)
+            _same_rounds(got, g["rounds"])
+            if mode == "empty":
+                _counters_equal(stats, g, 3)
+        again, _, final2 = s.wsc(3, 1, 10, target=I.target_covered, initial_uncovered=final)
+    assert again == []
+    assert np.array_equal(final2, final)
+
+
+def test_pair_list_regrowth_two_phase_graphs(pdfs):
+    """h = 4 two-phase walk with a 64-pair list: the sizing pass and the run
+    grow it; plain and replayed from captured graphs on a caller stream."""
+    import torch
+    I = synth.random_tiny(121, 1200, 150, 40, 0.02, 4)
+    T, N = I.packed()
+    exp = cpu.wsc(T, N, I.n_tumor, I.n_normal, 4, 1, 10, max_rounds=3, mode="empty")
+    with pdfs.Solver(T, N, I.n_tumor, I.n_normal, "empty", pair_cap=64) as s:
+        got, stats, _ = s.wsc(4, 1, 10, max_rounds=3)
+        _same_rounds(got, exp.rounds)
+        _counters_equal(stats, exp.counters, 4)
+    st = torch.cuda.Stream()
+    ctx = pdfs.pdfs_create(T, N, I.n_tumor, I.n_normal, "empty", 0, st.cuda_stream,
+                           pdfs.PDFS_OPT_GRAPHS, pair_cap=64)
+    try:
+        for _ in range(2):
+            got, stats, _ = pdfs.pdfs_wsc_run(ctx, 4, 1, 10, 0, 3, n_tumor=I.n_tumor)
+            _same_rounds(got, exp.rounds)
+            _counters_equal(stats, exp.counters, 4)
+    finally:
+        pdfs.pdfs_destroy(ctx)
+
+
 def test_device_inputs_and_stream(pdfs):
     import torch
     I = synth.random_tiny(55, 80, 190, 70, 0.15, 3)
