@@ -127,6 +127,8 @@ typedef struct {
     int32_t fp;                     /* normal samples covered                    */
     int32_t tn;                     /* n_normal - fp                             */
     int32_t uncovered_before;       /* |U| at the start of the round             */
+    int32_t newly_covered;          /* tumour samples the round adds to the cover
+                                       (U loses exactly the tp samples)         */
     int64_t score_num;              /* S = p*tp + q*tn                           */
     int64_t score_den;              /* q*(uncovered_before + n_normal); F = num/den */
 } pdfs_combo;

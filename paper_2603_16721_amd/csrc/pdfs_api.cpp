@@ -632,6 +632,7 @@ void fill_combo(pdfs_combo* o, const RoundRecord& r, int h) {
   }
   o->tp = r.tp; o->fp = r.fp; o->tn = r.tn;
   o->uncovered_before = r.uncovered_before;
+  o->newly_covered = r.found ? r.tp : 0;
   o->score_num = r.score_num; o->score_den = r.score_den;
 }
 

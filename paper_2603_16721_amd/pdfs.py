@@ -51,8 +51,8 @@ class pdfs_combo(ctypes.Structure):
     _fields_ = [("h", ctypes.c_int32), ("genes", ctypes.c_int32 * MAX_H),
                 ("sorted_idx", ctypes.c_int32 * MAX_H), ("tp", ctypes.c_int32),
                 ("fp", ctypes.c_int32), ("tn", ctypes.c_int32),
-                ("uncovered_before", ctypes.c_int32), ("score_num", ctypes.c_int64),
-                ("score_den", ctypes.c_int64)]
+                ("uncovered_before", ctypes.c_int32), ("newly_covered", ctypes.c_int32),
+                ("score_num", ctypes.c_int64), ("score_den", ctypes.c_int64)]
 
 
 class pdfs_stats(ctypes.Structure):
@@ -221,7 +221,8 @@ def combo_dict(c: pdfs_combo):
     h = c.h
     return {"genes": [int(g) for g in c.genes[:h]], "sorted_idx": [int(g) for g in c.sorted_idx[:h]],
             "tp": int(c.tp), "fp": int(c.fp), "tn": int(c.tn), "score_num": int(c.score_num),
-            "score_den": int(c.score_den), "uncovered_before": int(c.uncovered_before)}
+            "score_den": int(c.score_den), "uncovered_before": int(c.uncovered_before),
+            "newly_covered": int(c.newly_covered)}
 
 
 def pdfs_best_combo(ctx, h, alpha_p, alpha_q, uncovered=None):

@@ -35,6 +35,12 @@ def _same_rounds(got, exp):
     for k, (g, e) in enumerate(zip(got, exp)):
         for key in KEYS:
             assert g[key] == e[key], (k, key, g, e)
+        if "newly_covered" in g:
+            # the round adds its tp samples to the cover, and the next round
+            # starts from what is left
+            assert g["newly_covered"] == e["tp"], (k, g)
+            if k + 1 < len(got):
+                assert got[k + 1]["uncovered_before"] == g["uncovered_before"] - g["newly_covered"]
 
 
 def _counters_equal(gpu_stats, oracle_counters, h):
