@@ -656,14 +656,22 @@ __device__ __forceinline__ void make_items_body(const Problem& P, const Work& w,
        blk += (unsigned long long)gridDim.x * (blockDim.x >> 6) * 64) {
     int mylo = 0, mylen = 0;
     const int nbat = (int)((nb - blk) < 64 ? (nb - blk) : 64);
-    for (int j = 0; j < nbat; ++j) {
-      const unsigned long long pi = (blk + j) * kPairBatch + lane;
-      int b = 0x7fffffff;
-      if (pi < np) b = (int)((list[pi] >> 16) & 0xffff);
-      for (int o = 32; o > 0; o >>= 1) b = min(b, __shfl_xor(b, o, 64));
-      if (lane == j) {
-        mylo = b + 1;
-        mylen = amax3 > mylo ? amax3 - mylo : 0;
+    // 16 batches' loads in flight before their reductions
+    for (int j0 = 0; j0 < nbat; j0 += 16) {
+      int bv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const unsigned long long pi = (blk + j0 + u) * kPairBatch + lane;
+        bv[u] = (j0 + u < nbat && pi < np) ? (int)((list[pi] >> 16) & 0xffff) : 0x7fffffff;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        int b = bv[u];
+        for (int o = 32; o > 0; o >>= 1) b = min(b, __shfl_xor(b, o, 64));
+        if (lane == j0 + u && j0 + u < nbat) {
+          mylo = b + 1;
+          mylen = amax3 > mylo ? amax3 - mylo : 0;
+        }
       }
     }
     const unsigned long long n = mylen > 0 ? ((unsigned long long)mylen + chunk - 1) / chunk : 0;

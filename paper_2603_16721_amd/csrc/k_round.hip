@@ -16,11 +16,30 @@ namespace pdfs {
 
 namespace {
 
-__device__ __forceinline__ bool lex_less(const int32_t* x, const int32_t* y, int h) {
-  for (int i = 0; i < h; ++i) {
-    if (x[i] != y[i]) return x[i] < y[i];
+// Argmax order of the round's slots: higher S first, then the smaller tuple
+// over the first h indices.  Both the test and the update are written as
+// straight-line selects over a fixed trip count: the index arrays stay in
+// registers (a loop bounded by h indexes them at run time, which puts them in
+// scratch memory), and no field of the slot is updated under a branch of its
+// own (a short-circuit test with the copy under it was compiled into code
+// that left the TP of the old slot beside the indices of the new one).
+__device__ __forceinline__ bool slot_wins(const Slot& c, const Slot& b, int h) {
+  bool lt = false, decided = false;
+#pragma unroll
+  for (int i = 0; i < kMaxH; ++i) {
+    const bool d = !decided & (i < h) & (c.idx[i] != b.idx[i]);
+    lt = d ? (c.idx[i] < b.idx[i]) : lt;
+    decided = decided | d;
   }
-  return false;
+  return (c.s > b.s) | ((c.s == b.s) & (c.s >= 0) & lt);
+}
+
+__device__ __forceinline__ void take_if(Slot& b, const Slot& c, bool take) {
+  b.s = take ? c.s : b.s;
+  b.tp = take ? c.tp : b.tp;
+  b.fp = take ? c.fp : b.fp;
+#pragma unroll
+  for (int i = 0; i < kMaxH; ++i) b.idx[i] = take ? c.idx[i] : b.idx[i];
 }
 
 // ------------------------------------------------------------- ingest
@@ -231,7 +250,9 @@ __global__ void k_active_flags_m(const BatchDesc* __restrict__ bd) {
 
 // One block of 1024 threads: ordered compaction of the active flags, the
 // per-depth limits amax[l] and the depth-1/2 counters (Alg. 2 loop bounds:
-// depth l takes sorted indices up to G-h+l-1).
+// depth l takes sorted indices up to G-h+l-1).  Thread t owns one contiguous
+// range of genes, so one block-wide scan orders the whole list (a sweep of
+// 1024-gene chunks would wait on a load and two barriers per chunk).
 __device__ __forceinline__ void active_scan_body(const Problem& P, const Work& w) {
   __shared__ int wsum[16];
   __shared__ unsigned long long vsum[16];
@@ -240,28 +261,34 @@ __device__ __forceinline__ void active_scan_body(const Problem& P, const Work& w
   if (st->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int h = P.h;
-  int base = 0;
+  const int per = (P.G + 1023) >> 10;
+  const int g_lo = min(tid * per, P.G), g_hi = min(g_lo + per, P.G);
+  int mine = 0;
+#pragma unroll 8
+  for (int g = g_lo; g < g_hi; ++g) mine += w.flags[g] != 0;
+  int incl = mine;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int x = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += x;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int off = 0, base = 0;   // genes before this wave's; all active genes
+  for (int i = 0; i < 16; ++i) {
+    off += (i < wid) ? wsum[i] : 0;
+    base += wsum[i];
+  }
+  int pos = off + incl - mine;
   unsigned long long vis2 = 0;
   int ne1 = 0;   // genes meeting U within the depth-1 bound
-  for (int g0 = 0; g0 < P.G; g0 += 1024) {
-    int g = g0 + tid;
-    int f = (g < P.G) ? w.flags[g] : 0;
-    unsigned long long m = __ballot(f);
-    int pre = __popcll(m & ((1ull << lane) - 1));
-    if (lane == 0) wsum[wid] = __popcll(m);
-    __syncthreads();
-    int off = 0, tot = 0;
-    for (int i = 0; i < 16; ++i) {
-      off += (i < wid) ? wsum[i] : 0;
-      tot += wsum[i];
-    }
+#pragma unroll 8
+  for (int g = g_lo; g < g_hi; ++g) {
+    const int f = w.flags[g];
     if (f) {
-      w.act[base + off + pre] = g;
+      w.act[pos++] = g;
       if (h >= 2 && g <= P.G - h) vis2 += (unsigned long long)(P.G - h + 1 - g);
       if (f == 1 && g <= P.G - h) ++ne1;
     }
-    base += tot;
-    __syncthreads();
   }
   for (int o = 32; o > 0; o >>= 1) {
     vis2 += __shfl_xor(vis2, o, 64);
@@ -284,16 +311,12 @@ __device__ __forceinline__ void active_scan_body(const Problem& P, const Work& w
     st->cnt.nonempty[1] = (unsigned long long)n1;
     if (h >= 2) st->cnt.visited[2] = v;
   }
-  // amax[l] = number of active genes with sorted index <= G-h+l-1.  act is
-  // ascending, so it is a binary search per depth.
+  // amax[l] = number of active genes with sorted index <= G-h+l-1: all of
+  // them but those at the h-l highest indices
   if (tid >= 1 && tid <= h) {
-    int lim = P.G - h + tid - 1;
-    int lo = 0, hi = base;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if (w.act[mid] <= lim) lo = mid + 1; else hi = mid;
-    }
-    st->amax[tid] = lo;
+    int above = 0;
+    for (int g = max(P.G - h + tid, 0); g < P.G; ++g) above += w.flags[g] != 0;
+    st->amax[tid] = base - above;
   }
 }
 
@@ -464,7 +487,7 @@ __device__ __forceinline__ void finish_round_body(const Problem& P, const Work& 
     const int n = w.slot_log ? min((int)st->nlog[ph], kLogCap) : kSlotsPerPhase;
     for (int i = tid; i < n; i += 1024) {
       Slot c = src[i];
-      if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less(c.idx, b.idx, h))) b = c;
+      take_if(b, c, slot_wins(c, b, h));
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -473,7 +496,7 @@ __device__ __forceinline__ void finish_round_body(const Problem& P, const Work& 
     c.tp = __shfl_xor(b.tp, o, 64);
     c.fp = __shfl_xor(b.fp, o, 64);
     for (int i = 0; i < kMaxH; ++i) c.idx[i] = __shfl_xor(b.idx[i], o, 64);
-    if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less(c.idx, b.idx, h))) b = c;
+    take_if(b, c, slot_wins(c, b, h));
   }
   if (lane == 0) red[wid] = b;
   __syncthreads();
@@ -482,14 +505,16 @@ __device__ __forceinline__ void finish_round_body(const Problem& P, const Work& 
   if (tid == 0) {
     for (int i = 1; i < 16; ++i) {
       Slot c = red[i];
-      if (c.s > b.s || (c.s == b.s && c.s >= 0 && lex_less(c.idx, b.idx, h))) b = c;
+      take_if(b, c, slot_wins(c, b, h));
     }
     int ok = b.s >= 0;
     if (ok) {
       // a slot index outside the active list would mean a corrupt slot
       const int nA = st->nA;
-      for (int i = 0; i < h; ++i)
-        if (b.idx[i] < 0 || b.idx[i] >= nA || (i > 0 && b.idx[i] <= b.idx[i - 1])) ok = 0;
+#pragma unroll
+      for (int i = 0; i < kMaxH; ++i)
+        if (i < h && (b.idx[i] < 0 || b.idx[i] >= nA || (i > 0 && b.idx[i] <= b.idx[i - 1])))
+          ok = 0;
       if (b.tp <= 0) ok = 0;
       if (!ok) st->overflow |= 2;
     }
@@ -500,7 +525,7 @@ __device__ __forceinline__ void finish_round_body(const Problem& P, const Work& 
   b = s_best;
   const int found = s_found;
   if (found && tid < h) {
-    const int si = w.act[b.idx[tid]];
+    const int si = w.act[s_best.idx[tid]];
     s_sidx[tid] = si;
     s_gene[tid] = w.perm[si];
   }

@@ -5,12 +5,26 @@
 
 namespace pdfs {
 
+// The test and the update are straight-line selects: no field of a slot is
+// copied under a branch of its own, so every field of the winner moves
+// together.
 __device__ __forceinline__ bool slot_better(const Slot& c, const Slot& b) {
-  if (c.s != b.s) return c.s > b.s;
-  if (c.s < 0) return false;
-  for (int i = 0; i < kMaxH; ++i)
-    if (c.idx[i] != b.idx[i]) return c.idx[i] < b.idx[i];
-  return false;
+  bool lt = false, decided = false;
+#pragma unroll
+  for (int i = 0; i < kMaxH; ++i) {
+    const bool d = !decided & (c.idx[i] != b.idx[i]);
+    lt = d ? (c.idx[i] < b.idx[i]) : lt;
+    decided = decided | d;
+  }
+  return (c.s > b.s) | ((c.s == b.s) & (c.s >= 0) & lt);
+}
+
+__device__ __forceinline__ void slot_take_if(Slot& b, const Slot& c, bool take) {
+  b.s = take ? c.s : b.s;
+  b.tp = take ? c.tp : b.tp;
+  b.fp = take ? c.fp : b.fp;
+#pragma unroll
+  for (int i = 0; i < kMaxH; ++i) b.idx[i] = take ? c.idx[i] : b.idx[i];
 }
 
 __device__ __forceinline__ Slot empty_slot() {
@@ -27,7 +41,7 @@ __device__ __forceinline__ Slot wave_best(Slot b) {
     c.tp = __shfl_xor(b.tp, o, 64);
     c.fp = __shfl_xor(b.fp, o, 64);
     for (int i = 0; i < kMaxH; ++i) c.idx[i] = __shfl_xor(b.idx[i], o, 64);
-    if (slot_better(c, b)) b = c;
+    slot_take_if(b, c, slot_better(c, b));
   }
   return b;
 }
@@ -43,7 +57,7 @@ __device__ __forceinline__ void block_best_to(Slot* dst, Slot b) {
   if (threadIdx.x == 0) {
     Slot r = red[0];
     for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
-      if (slot_better(red[i], r)) r = red[i];
+      slot_take_if(r, red[i], slot_better(red[i], r));
     *dst = r;
   }
 }

@@ -84,6 +84,34 @@ def test_wsc_tiny(pdfs, case, mode):
         _counters_equal(stats, exp.counters, h)
 
 
+# With p = 0 every leaf without false positives scores the same, so the argmax
+# is decided by the tuple order alone and almost every slot comparison is a
+# tie on S: the winner's TP, FP and indices must still come from one leaf.
+# Which block holds which leaf varies from run to run, so each case runs
+# several times.
+TIES = [
+    # seed, G, n_tumor, n_normal, density, h, alpha
+    (107, 64, 129, 300, 0.2, 3, (0, 1)),
+    (114, 60, 100, 40, 0.2, 4, (0, 1)),
+    (121, 90, 200, 0, 0.15, 3, (0, 1)),
+    (122, 70, 64, 20, 0.25, 2, (0, 3)),
+]
+
+
+@pytest.mark.parametrize("case", TIES, ids=[f"s{c[0]}_G{c[1]}_h{c[5]}" for c in TIES])
+@pytest.mark.parametrize("mode", ["empty", "bound"])
+def test_wsc_score_ties(pdfs, case, mode):
+    seed, G, nt, nn, d, h, (p, q) = case
+    I = synth.random_tiny(seed, G, nt, nn, d, h, alpha=(p, q))
+    T, N = I.packed()
+    exp = cpu.wsc(T, N, nt, nn, h, p, q, mode="empty")
+    for _ in range(4):
+        with pdfs.Solver(T, N, nt, nn, mode) as s:
+            got, stats, final = s.wsc(h, p, q)
+        _same_rounds(got, exp.rounds)
+        assert np.array_equal(final, exp.final_uncovered)
+
+
 # h = 5..9: the ring walk below the pair level (every mode; BOUND runs the same walk)
 DEEP = [
     # seed, G, n_tumor, n_normal, density, h, alpha
