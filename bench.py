@@ -241,9 +241,9 @@ def bench_batched(pdfs, data, modes=("bound", "empty")):
                 plain_rounds.append([(x["genes"], x["tp"], x["fp"]) for x in r])
         row = {"plain_serial_ms": plain_ms}
         reps = 3 if mode == "bound" else 1
-        for name, streams_only in (("streams", True), ("one_launch_per_step", False)):
+        for name, path in (("streams", "streams"), ("one_launch_per_step", "one_launch")):
             b = pdfs.pdfs_batch_create([(T, N, nt, nn) for (_, T, N, nt, nn, _) in data], mode,
-                                       autotune=True, streams_only=streams_only)
+                                       autotune=True, path=path)
             try:
                 pdfs.pdfs_batch_run(b, hs, 1, 10, n_tumors=ncap)   # warm + tune
                 times = []
@@ -258,6 +258,9 @@ def bench_batched(pdfs, data, modes=("bound", "empty")):
                          "same_results": same, "rounds": st["rounds"]}
             print(f"[bench] batched {mode} {name}: {min(times):.1f} ms vs plain serial "
                   f"{plain_ms:.1f} ms", file=sys.stderr, flush=True)
+        # the path a batch takes by default for this mode (path="auto")
+        row["default_path"] = "one_launch_per_step" if mode == "bound" else "streams"
+        row["default_speedup_vs_plain_serial"] = row[row["default_path"]]["speedup_vs_plain_serial"]
         out[mode] = row
     return out
 

@@ -259,16 +259,26 @@ int32_t pdfs_measure_int_peak(int32_t device, double *lane_ops_per_s);
  * seed pairs in bound mode) is chosen per instance class by the tuner below
  * when the batch is created with PDFS_OPT_AUTOTUNE. */
 #define PDFS_OPT_AUTOTUNE 4
-/* Batched runs of instances with h in {3, 4} under PDFS_PRUNE_EMPTY or
- * PDFS_PRUNE_BOUND go through one launch per round step over all instances
- * (up to 64): every light step covers every instance with a block row each,
- * each depth-first step drains one shared work queue of all live instances'
- * work items (the ordering of Sec. III-D's request-driven chunks), and the
- * round's launches are one captured HIP graph replayed until every
- * instance's stop flag is set; the row width of a chunk of rounds is the
- * largest any live instance needs.  Other batches, or this flag, run each
- * instance's own launches concurrently on the batch's streams instead. */
+/* Two ways to run a batch; by default each run takes the one that measures
+ * faster for its pruning mode.
+ * One launch per round step over all instances (default under
+ * PDFS_PRUNE_BOUND; only for batches of up to 64 instances, all with h in
+ * {3, 4}, under PDFS_PRUNE_EMPTY or PDFS_PRUNE_BOUND): every light step
+ * covers every instance with a block row each, each depth-first step drains
+ * one shared work queue of all live instances' work items (the ordering of
+ * Sec. III-D's request-driven chunks), and the round's launches are one
+ * captured HIP graph replayed until every instance's stop flag is set; the
+ * row width of a chunk of rounds is the largest any live instance needs.
+ * Each instance's own launches concurrently on the batch's streams (default
+ * otherwise): under PDFS_PRUNE_EMPTY a round of a large instance fills the
+ * device by itself, and instances that run independently overlap one
+ * instance's narrow tail rounds with another's wide ones, where one launch
+ * per step makes every instance wait for the slowest at each step.
+ * PDFS_OPT_BATCH_STREAMS asks for the streams, PDFS_OPT_BATCH_ONE_LAUNCH for
+ * one launch per step where the batch allows it (streams otherwise); both
+ * together are PDFS_ERR_INVALID_ARG. */
 #define PDFS_OPT_BATCH_STREAMS 16
+#define PDFS_OPT_BATCH_ONE_LAUNCH 32
 
 typedef struct pdfs_batch pdfs_batch;
 

@@ -251,6 +251,7 @@ struct pdfs_batch {
   std::vector<hipEvent_t> join_ev;
   int n_alloc = 0;                           // instances the batched buffers hold
   bool streams_only = false;                 // PDFS_OPT_BATCH_STREAMS: no batched launches
+  bool one_launch = false;                   // PDFS_OPT_BATCH_ONE_LAUNCH: batched launches in every mode
 };
 
 namespace {
@@ -714,6 +715,12 @@ int32_t pdfs_batch_create(const pdfs_matrix* inst, int32_t n, const pdfs_options
   b->device = opt ? opt->device : 0;
   b->autotune = opt && (opt->flags & PDFS_OPT_AUTOTUNE);
   b->streams_only = opt && (opt->flags & PDFS_OPT_BATCH_STREAMS);
+  b->one_launch = opt && (opt->flags & PDFS_OPT_BATCH_ONE_LAUNCH);
+  if (b->streams_only && b->one_launch) {
+    delete b;
+    return ctx_fail(nullptr, PDFS_ERR_INVALID_ARG,
+                    "PDFS_OPT_BATCH_STREAMS and PDFS_OPT_BATCH_ONE_LAUNCH exclude each other");
+  }
   if (hipSetDevice(b->device) != hipSuccess) {
     delete b;
     return ctx_fail(nullptr, PDFS_ERR_DEVICE, "hipSetDevice failed");
@@ -761,8 +768,11 @@ int32_t pdfs_batch_run(pdfs_batch* b, const int32_t* h, uint32_t p, uint32_t q,
   if (b->autotune)
     for (int i = 0; i < n; ++i) autotune(b->ctx[i], h[i], p, q);
   // one launch per round step over every instance when all take it (h = 3, 4
-  // with empty or bound pruning); the stream-parallel runs below otherwise
-  bool multi = n <= kMaxBatch && b->ctx[0]->prune_mode != PDFS_PRUNE_NONE && !b->streams_only;
+  // with empty or bound pruning) and it is the faster way for the mode (bound
+  // pruning) or asked for; the stream-parallel runs below otherwise
+  const int pm = b->ctx[0]->prune_mode;
+  bool multi = n <= kMaxBatch && pm != PDFS_PRUNE_NONE && !b->streams_only &&
+               (b->one_launch || pm == PDFS_PRUNE_BOUND);
   for (int i = 0; i < n; ++i)
     multi = multi && (h[i] == 3 || h[i] == 4) && b->ctx[i]->tn_literal == b->ctx[0]->tn_literal;
   if (multi) return run_multi(b, h, p, q, target, outs, caps, n_outs, stats, t0);

@@ -78,6 +78,8 @@ PDFS_OPT_GRAPHS = 2
 PDFS_OPT_AUTOTUNE = 4
 PDFS_OPT_TN_LITERAL = 8
 PDFS_OPT_BATCH_STREAMS = 16
+PDFS_OPT_BATCH_ONE_LAUNCH = 32
+BATCH_PATHS = {"auto": 0, "streams": PDFS_OPT_BATCH_STREAMS, "one_launch": PDFS_OPT_BATCH_ONE_LAUNCH}
 
 
 def _load():
@@ -324,11 +326,15 @@ class Solver:
 
 
 def pdfs_batch_create(instances, prune_mode="bound", device=0, autotune=False,
-                      streams_only=False, pair_cap=0):
+                      path="auto", pair_cap=0):
     """instances: list of (tumor, normal, n_tumor, n_normal) host arrays.  Returns a handle.
-    streams_only: each instance's own launches on the batch's streams instead of one
-    launch per round step over all instances.  pair_cap: every instance's initial
-    pair-list capacity (pdfs_options.pair_cap)."""
+    path: "auto" (the faster way for the mode: one launch per round step over all
+    instances under bound pruning, each instance's own launches on the batch's
+    streams otherwise), "streams" or "one_launch" (PDFS_OPT_BATCH_STREAMS /
+    PDFS_OPT_BATCH_ONE_LAUNCH).  pair_cap: every instance's initial pair-list
+    capacity (pdfs_options.pair_cap)."""
+    if path not in BATCH_PATHS:
+        raise ValueError(f"path must be one of {sorted(BATCH_PATHS)}")
     mats, keep = [], []
     for (T, N, nt, nn) in instances:
         m, k = _matrix_arg(T, N, nt, nn)
@@ -337,8 +343,8 @@ def pdfs_batch_create(instances, prune_mode="bound", device=0, autotune=False,
     arr = (pdfs_matrix * len(mats))(*mats)
     mode = PRUNE_MODES[prune_mode] if isinstance(prune_mode, str) else int(prune_mode)
     opt = pdfs_options(prune_mode=mode, device=device, stream=None,
-                       flags=(PDFS_OPT_AUTOTUNE if autotune else 0) |
-                       (PDFS_OPT_BATCH_STREAMS if streams_only else 0), pair_cap=pair_cap)
+                       flags=(PDFS_OPT_AUTOTUNE if autotune else 0) | BATCH_PATHS[path],
+                       pair_cap=pair_cap)
     out = ctypes.c_void_p()
     rc = lib.pdfs_batch_create(arr, len(mats), ctypes.byref(opt), ctypes.byref(out))
     del keep

@@ -82,3 +82,24 @@ def test_binding_layout_matches_header(tmp_path):
             assert got[(f"{n}.{f[0]}", "off")] == getattr(cls, f[0]).offset, (n, f[0])
     for n, v in consts.items():
         assert got[(n, "val")] == v, n
+
+
+def test_batch_path_flags_exclude_each_other_without_gpu():
+    """Asking for both batch paths is rejected before any device call; the
+    binding rejects unknown path names."""
+    import numpy as np
+    import pytest
+    from paper_2603_16721_amd import pdfs
+    T = np.ones((3, 1), dtype=np.uint64)
+    N = np.ones((3, 1), dtype=np.uint64)
+    m, keep = pdfs._matrix_arg(T, N, 1, 1)
+    arr = (pdfs.pdfs_matrix * 1)(m)
+    opt = pdfs.pdfs_options(prune_mode=pdfs.PRUNE_MODES["empty"], device=0, stream=None,
+                            flags=pdfs.PDFS_OPT_BATCH_STREAMS | pdfs.PDFS_OPT_BATCH_ONE_LAUNCH)
+    out = ctypes.c_void_p()
+    rc = pdfs.lib.pdfs_batch_create(arr, 1, ctypes.byref(opt), ctypes.byref(out))
+    assert rc == pdfs.PDFS_ERR_INVALID_ARG and not out.value
+    assert b"exclude each other" in pdfs.lib.pdfs_batch_last_error(None)
+    with pytest.raises(ValueError):
+        pdfs.pdfs_batch_create([(T, N, 1, 1)], "empty", path="one-launch")
+    del keep

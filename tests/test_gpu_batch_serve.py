@@ -31,11 +31,11 @@ def _compact(rounds):
     return [[*r["genes"], r["tp"], r["fp"], r["score_num"]] for r in rounds]
 
 
-def _batch(pdfs, idx, autotune=False, mode="bound", streams_only=False, pair_cap=0):
+def _batch(pdfs, idx, autotune=False, mode="bound", path="one_launch", pair_cap=0):
     insts = [synth.batched_instance(i) for i in idx]
     packed = [(I.packed(), I) for I in insts]
     b = pdfs.pdfs_batch_create([(T, N, I.n_tumor, I.n_normal) for (T, N), I in packed], mode,
-                               autotune=autotune, streams_only=streams_only, pair_cap=pair_cap)
+                               autotune=autotune, path=path, pair_cap=pair_cap)
     return b, insts
 
 
@@ -77,13 +77,14 @@ def test_batched_autotune_and_empty_mode_same_results(pdfs, tmp_path, monkeypatc
     assert {e["mode"] for e in entries} == {1, 2}
 
 
+@pytest.mark.parametrize("path", ["streams", "auto"])
 @pytest.mark.parametrize("mode", ["bound", "empty"])
-def test_batched_streams_path_matches_oracle(pdfs, mode):
-    """The stream-parallel batched runs (each instance's own launches) give the
-    same results as the one-launch-per-step runs and the oracle."""
+def test_batched_streams_path_matches_oracle(pdfs, mode, path):
+    """The stream-parallel batched runs (each instance's own launches), and the
+    path a batch takes by default for its mode, give the oracle's results."""
     gold = _golden("batched")
     idx = [2, 5, 12, 20]
-    b, insts = _batch(pdfs, idx, mode=mode, streams_only=True)
+    b, insts = _batch(pdfs, idx, mode=mode, path=path)
     try:
         res, _ = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
                                      n_tumors=[I.n_tumor for I in insts])
@@ -93,16 +94,16 @@ def test_batched_streams_path_matches_oracle(pdfs, mode):
         assert _compact(res[k]) == gold[str(i)]["rounds"], (mode, i)
 
 
-@pytest.mark.parametrize("streams_only", [False, True])
+@pytest.mark.parametrize("path", ["one_launch", "streams"])
 @pytest.mark.parametrize("mode", ["bound", "empty"])
-def test_batched_pair_list_regrowth(pdfs, mode, streams_only):
+def test_batched_pair_list_regrowth(pdfs, mode, path):
     """Every instance starts with a 64-pair list: the rounds that emit more
     grow their instance's list and run again (one launch per round step over
     all instances, or each instance on the batch's streams); the results are
     the oracle's."""
     gold = _golden("batched")
     idx = [0, 3, 5, 12, 16, 21]
-    b, insts = _batch(pdfs, idx, mode=mode, streams_only=streams_only, pair_cap=64)
+    b, insts = _batch(pdfs, idx, mode=mode, path=path, pair_cap=64)
     try:
         res, _ = pdfs.pdfs_batch_run(b, [I.h for I in insts], 1, 10,
                                      n_tumors=[I.n_tumor for I in insts])
