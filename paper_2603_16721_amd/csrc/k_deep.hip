@@ -285,25 +285,24 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
       }
       const int fp = leaf_fp(z, NAc + (size_t)dd * kMaxWN32, lit);
       const int sc = P.p * tp + P.q * (P.n_normal - fp);
-      bool take_it = sc > bs;
-      if (sc == bs) {
-        // equal score: the smaller tuple (lexicographic, sorted indices)
-        int cmp = 0;
+      // equal score: the smaller tuple (lexicographic, sorted indices); the
+      // test and the update of every field are straight-line selects under
+      // one mask, as in the slot argmax
+      int cmp = 0;
 #pragma unroll
-        for (int i = 0; i < kMaxH; ++i) {
-          if (cmp == 0 && i < h) {
-            const int x = i < h - 1 ? pix[i] : dd;
-            cmp = x < bidx[i] ? -1 : (x > bidx[i] ? 1 : 0);
-          }
-        }
-        take_it = cmp < 0;
+      for (int i = 0; i < kMaxH; ++i) {
+        const int x = i < h - 1 ? pix[i] : dd;
+        const int ci = x < bidx[i] ? -1 : (x > bidx[i] ? 1 : 0);
+        cmp = (cmp == 0) & (i < h) ? ci : cmp;
       }
-      if (take_it) {
-        bs = sc;
-        btp = tp;
-        bfp = fp;
+      const bool take_it = (sc > bs) | ((sc == bs) & (cmp < 0));
+      bs = take_it ? sc : bs;
+      btp = take_it ? tp : btp;
+      bfp = take_it ? fp : bfp;
 #pragma unroll
-        for (int i = 0; i < kMaxH; ++i) bidx[i] = i < h - 1 ? pix[i] : (i == h - 1 ? dd : 0);
+      for (int i = 0; i < kMaxH; ++i)
+        bidx[i] = take_it ? (i < h - 1 ? pix[i] : (i == h - 1 ? dd : 0)) : bidx[i];
+      if (take_it) {
         if (bound) {
           const unsigned long long key = leaf_key(sc, pix[0], pix[1]);
           if (key > inc) {

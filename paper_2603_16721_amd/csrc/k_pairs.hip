@@ -171,9 +171,14 @@ __device__ __forceinline__ void pairs_body(const Problem& P, const Work& w) {
                                  ? w.ncount[w.act[i]] + w.ncount[sj] - accn[m][n][r]
                                  : accn[m][n][r];
               const int s = P.p * c + P.q * (P.n_normal - fp);
-              if (s > bs || (s == bs && (i < bi_ || (i == bi_ && j < bj_)))) {
-                bs = s; btp = c; bfp = fp; bi_ = i; bj_ = j;
-              }
+              // one mask for every field (straight-line selects)
+              const bool take =
+                  (s > bs) | ((s == bs) & ((i < bi_) | ((i == bi_) & (j < bj_))));
+              bs = take ? s : bs;
+              btp = take ? c : btp;
+              bfp = take ? fp : bfp;
+              bi_ = take ? i : bi_;
+              bj_ = take ? j : bj_;
             }
           } else if (emit) {
             ++nhit;

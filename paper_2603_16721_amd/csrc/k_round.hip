@@ -392,7 +392,12 @@ __global__ __launch_bounds__(256) void k_h1(Problem P, Work w) {
     for (int k = 0; k < W32; ++k) tp += __popc(w.TA[(size_t)a * W32 + k]);
     for (int k = 0; k < kMaxWN32; ++k) fp += __popc(w.NA[(size_t)a * kMaxWN32 + k]);
     int s = P.p * tp + P.q * (P.n_normal - fp);
-    if (tp > 0 && (s > bs || (s == bs && a < bi))) { bs = s; btp = tp; bfp = fp; bi = a; }
+    // one mask for every field (straight-line selects, as in the slot argmax)
+    const bool take = (tp > 0) & ((s > bs) | ((s == bs) & (a < bi)));
+    bs = take ? s : bs;
+    btp = take ? tp : btp;
+    bfp = take ? fp : bfp;
+    bi = take ? a : bi;
   }
   Slot sl = empty_slot();
   if (bs >= 0) { sl.s = bs; sl.tp = btp; sl.fp = bfp; sl.idx[0] = bi; }

@@ -85,8 +85,9 @@ def test_wsc_tiny(pdfs, case, mode):
 
 
 # With p = 0 every leaf without false positives scores the same, so the argmax
-# is decided by the tuple order alone and almost every slot comparison is a
-# tie on S: the winner's TP, FP and indices must still come from one leaf.
+# is decided by the tuple order alone and almost every comparison of two
+# candidates (per lane, wave, block and round, at every h) is a tie on S: the
+# winner's TP, FP and indices must still come from one leaf.
 # Which block holds which leaf varies from run to run, so each case runs
 # several times.
 TIES = [
@@ -95,6 +96,9 @@ TIES = [
     (114, 60, 100, 40, 0.2, 4, (0, 1)),
     (121, 90, 200, 0, 0.15, 3, (0, 1)),
     (122, 70, 64, 20, 0.25, 2, (0, 3)),
+    (123, 45, 150, 40, 0.2, 1, (0, 1)),
+    (124, 40, 100, 30, 0.25, 5, (0, 2)),
+    (206, 36, 130, 0, 0.3, 6, (0, 1)),
 ]
 
 
