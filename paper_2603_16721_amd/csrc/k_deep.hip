@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
       for (int i = 0; i < kMaxH; ++i) {
         const int x = i < h - 1 ? pix[i] : dd;
         const int ci = x < bidx[i] ? -1 : (x > bidx[i] ? 1 : 0);
-        cmp = (cmp == 0) & (i < h) ? ci : cmp;
+        cmp = ((cmp == 0) & (i < h)) ? ci : cmp;
       }
       const bool take_it = (sc > bs) | ((sc == bs) & (cmp < 0));
       bs = take_it ? sc : bs;
