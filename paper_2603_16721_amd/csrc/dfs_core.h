@@ -432,7 +432,9 @@ __device__ __forceinline__ unsigned long long triple_entry(int a, int b, int c) 
 }
 
 // Appends q[0, n) to the round's list (one atomic per call) and adds the
-// per-c counts, one atomic per run of equal c among 64 consecutive entries.
+// per-c counts, one atomic per run of equal c among 64 consecutive entries;
+// the count an atomic returns is the run's first rank among the entries of
+// its c, kept with each entry so that the bucketing needs no atomics.
 __device__ __forceinline__ void append_staged(const Work& w, RoundState* st,
                                               const unsigned long long* q, int n, int lane) {
   unsigned long long base = 0;
@@ -449,11 +451,17 @@ __device__ __forceinline__ void append_staged(const Work& w, RoundState* st,
     const unsigned long long H = __ballot(head);
     // valid lanes form a prefix; counted with the whole wave active
     const int nvalid = __popcll(__ballot(v));
+    uint32_t r0 = 0;
     if (head) {
       const unsigned long long above = H & ~((2ull << lane) - 1ull);
       const int next = above ? __builtin_ctzll(above) : nvalid;
-      atomicAdd(&w.c_hist[c], (uint32_t)(next - lane));
+      r0 = atomicAdd(&w.c_hist[c], (uint32_t)(next - lane));
     }
+    // the run's head: highest head at or below this lane (lane 0 always is one)
+    const unsigned long long below = H & ((2ull << lane) - 1ull);
+    const int hl = below ? 63 - __builtin_clzll(below) : 0;
+    const uint32_t rank = (uint32_t)__shfl((int)r0, hl, 64) + (uint32_t)(lane - hl);
+    if (v) w.tri_rank[base + i] = rank;
   }
 }
 

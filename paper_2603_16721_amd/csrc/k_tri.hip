@@ -144,34 +144,17 @@ __global__ __launch_bounds__(1024) void k_scan_c_m(const BatchDesc* __restrict__
   scan_c_body(bd[blockIdx.y].w);
 }
 
-// Scatter into c buckets: each run of equal c among 64 consecutive entries
-// takes its slots with one atomic on the bucket's cursor.
+// Scatter into c buckets: entry i goes to its bucket's offset plus the rank
+// it was given when it was counted (no atomics; coalesced reads).
 __device__ __forceinline__ void scatter_c_body(const Work& w) {
   RoundState* st = w.st;
   if (st->done || w.tri_cap == 0) return;
-  const int lane = threadIdx.x & 63;
   const unsigned long long n = st->n_tri < w.tri_cap ? st->n_tri : w.tri_cap;
-  for (unsigned long long base = (unsigned long long)(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6)) * kWave;
-       base < n; base += (unsigned long long)gridDim.x * kBlock) {
-    const unsigned long long i = base + lane;
-    const bool v = i < n;
-    const unsigned long long e = v ? w.tri[i] : 0ull;
-    const int c = v ? (int)(e >> 32) : -1;
-    const int cprev = __shfl_up(c, 1, 64);
-    const bool head = v && (lane == 0 || c != cprev);
-    const unsigned long long H = __ballot(head);
-    uint32_t pos0 = 0;
-    if (head) {
-      const unsigned long long above = H & ~((2ull << lane) - 1ull);
-      const int nv = n - base < (unsigned long long)kWave ? (int)(n - base) : kWave;
-      const int next = above ? __builtin_ctzll(above) : nv;
-      pos0 = atomicAdd(&w.c_hist[c], (uint32_t)(next - lane));
-    }
-    // the run's head: highest head at or below this lane (lane 0 always is one)
-    const unsigned long long below = H & ((2ull << lane) - 1ull);
-    const int hl = below ? 63 - __builtin_clzll(below) : 0;
-    const uint32_t p0 = (uint32_t)__shfl((int)pos0, hl, 64);
-    if (v) w.tri_s[(unsigned long long)p0 + (unsigned long long)(lane - hl)] = e;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * kBlock) {
+    const unsigned long long e = w.tri[i];
+    const int c = (int)((e >> 32) & 0xffff);
+    w.tri_s[(unsigned long long)w.c_hist[c] + w.tri_rank[i]] = e;
   }
 }
 

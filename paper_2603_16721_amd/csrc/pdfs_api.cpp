@@ -57,7 +57,7 @@ void release(pdfs_ctx* c) {
   void* ptrs[] = {c->Ts, c->Ns, c->perm, c->ncount, c->U, c->cols, c->act, c->flags, c->TA, c->NA,
                   c->A8, c->N8, c->pairs, c->work_pairs, c->seed_pairs, c->hist, c->cursors,
                   c->items, c->slots, c->tallies, c->st, c->recs, c->tri, c->tri_s,
-                  c->c_hist, c->deepq};
+                  c->tri_rank, c->c_hist, c->deepq};
   for (void* p : ptrs) dfree(c, p);
   if (c->h_slots && c->own_h_st) (void)hipHostFree(c->h_slots);
   for (auto& set : c->ev)
@@ -82,7 +82,8 @@ static int32_t grow_for_all_genes(pdfs_ctx* c) {
   CK(c, hipStreamSynchronize(c->stream));
   void** bufs[] = {(void**)&c->TA, (void**)&c->NA, (void**)&c->A8, (void**)&c->N8,
                    (void**)&c->pairs, (void**)&c->work_pairs, (void**)&c->seed_pairs,
-                   (void**)&c->items, (void**)&c->tri, (void**)&c->tri_s, (void**)&c->c_hist};
+                   (void**)&c->items, (void**)&c->tri, (void**)&c->tri_s, (void**)&c->tri_rank,
+                   (void**)&c->c_hist};
   for (void** b : bufs) {
     dfree(c, *b);
     *b = nullptr;
@@ -194,7 +195,7 @@ Work make_work(pdfs_ctx* c, int w64, int target) {
   w.pair_cap = c->pair_cap; w.item_cap = c->item_cap;
   w.w64 = w64; w.wn32 = 2 * c->wn; w.target = target;
   w.chunk = c->chunk_items; w.seed_n = c->seed_pairs_n; w.long_stream = c->long_stream;
-  w.tri = c->tri; w.tri_s = c->tri_s; w.c_hist = c->c_hist;
+  w.tri = c->tri; w.tri_s = c->tri_s; w.tri_rank = c->tri_rank; w.c_hist = c->c_hist;
   w.tri_cap = c->two_phase ? c->tri_cap : 0;
   w.deepq = c->deepq;
   w.slot_log = nullptr;
@@ -378,16 +379,20 @@ static int32_t size_triples(pdfs_ctx* c, int h, int n_unc) {
     const unsigned long long cap = need + need / 16 + 1024;
     size_t free_b = 0, total_b = 0;
     CK(c, hipMemGetInfo(&free_b, &total_b));
-    if (cap >= (1ull << 32) || 2 * cap * sizeof(unsigned long long) > free_b / 2) return PDFS_OK;
+    const size_t per_entry = 2 * sizeof(unsigned long long) + sizeof(uint32_t);
+    if (cap >= (1ull << 32) || cap * per_entry > free_b / 2) return PDFS_OK;
     dfree(c, c->tri);
     dfree(c, c->tri_s);
+    dfree(c, c->tri_rank);
     c->tri = c->tri_s = nullptr;
+    c->tri_rank = nullptr;
     c->tri_cap = 0;
     // captured rounds hold the old list addresses
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     CK(c, dalloc(c, &c->tri, (size_t)cap));
     CK(c, dalloc(c, &c->tri_s, (size_t)cap));
+    CK(c, dalloc(c, &c->tri_rank, (size_t)cap));
     c->tri_cap = cap;
   }
   c->two_phase = true;

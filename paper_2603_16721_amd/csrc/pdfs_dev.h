@@ -186,9 +186,11 @@ struct Work {
   int32_t seed_n;    // bound mode: pairs expanded in the seed phase
   int32_t long_stream;   // two-phase depth 4: prefixes with at least this many
                          // depth-4 candidates are listed for the tile kernel
-  // two-phase depth-4: listed triples a | b << 16 | c << 32, the same sorted
-  // by c, and per-c counts (then bucket offsets), nA entries
+  // two-phase depth-4: listed triples a | b << 16 | c << 32, each entry's rank
+  // among the listed entries of its c (taken when it is counted), the same
+  // sorted by c, and per-c counts (then bucket offsets), nA entries
   unsigned long long* tri;
+  uint32_t* tri_rank;
   unsigned long long* tri_s;
   uint32_t* c_hist;
   unsigned long long tri_cap;   // 0: count only

@@ -82,6 +82,7 @@ struct pdfs_ctx {
   // counts, sized at run start for the run's first (largest) round
   unsigned long long* tri = nullptr;
   unsigned long long* tri_s = nullptr;
+  uint32_t* tri_rank = nullptr;
   uint32_t* c_hist = nullptr;
   uint32_t* deepq = nullptr;   // h >= 5 leaf-prefix rings
   unsigned long long tri_cap = 0;

@@ -197,6 +197,7 @@ int32_t pdfs_best_combo_noalloc(pdfs_ctx* c, int32_t h, uint32_t p, uint32_t q,
   w.item_cap = L.item_cap;
   // single-kernel depth 4 (no prefix lists), no deep-walk rings
   w.tri = w.tri_s = nullptr;
+  w.tri_rank = nullptr;
   w.c_hist = nullptr;
   w.tri_cap = 0;
   w.deepq = nullptr;
