@@ -285,15 +285,17 @@ __global__ __launch_bounds__(256) void k_dfs_deep(Problem P, Work w, int phase) 
       }
       const int fp = leaf_fp(z, NAc + (size_t)dd * kMaxWN32, lit);
       const int sc = P.p * tp + P.q * (P.n_normal - fp);
-      // equal score: the smaller tuple (lexicographic, sorted indices); the
-      // test and the update of every field are straight-line selects under
-      // one mask, as in the slot argmax
+      // equal score: the smaller tuple (lexicographic, sorted indices),
+      // compared only on a tie; the update of every field is a straight-line
+      // select under one mask, as in the slot argmax
       int cmp = 0;
+      if (sc == bs) {
 #pragma unroll
-      for (int i = 0; i < kMaxH; ++i) {
-        const int x = i < h - 1 ? pix[i] : dd;
-        const int ci = x < bidx[i] ? -1 : (x > bidx[i] ? 1 : 0);
-        cmp = ((cmp == 0) & (i < h)) ? ci : cmp;
+        for (int i = 0; i < kMaxH; ++i) {
+          const int x = i < h - 1 ? pix[i] : dd;
+          const int ci = x < bidx[i] ? -1 : (x > bidx[i] ? 1 : 0);
+          cmp = ((cmp == 0) & (i < h)) ? ci : cmp;
+        }
       }
       const bool take_it = (sc > bs) | ((sc == bs) & (cmp < 0));
       bs = take_it ? sc : bs;
